@@ -1,0 +1,326 @@
+/*
+ * libtreebbox ORACLE -- test infrastructure only.
+ *
+ * A plain, single-threaded, obviously-sequential CPU implementation of what
+ * the GPU path computes.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  It shares no
+ * code, header or table with the GPU path.
+ *
+ * What it follows (Levien, "Fast GPU bounding boxes on tree-structured
+ * scenes", arXiv 2205.11659):
+ *  - The sequential stack algorithm of Fig. 1 (section "The parentheses
+ *    matching problem"): a stack seeded with -1; each element records the top
+ *    of the stack, opens push their own index, closes pop.  `pm` below is
+ *    exactly that output; `match` is the classical partner, which the same
+ *    section says is reconstructed from it.
+ *  - The Introduction's sequential bounding-box walk: each stack entry holds
+ *    one clip box and one blend box; clip nodes intersect, blends union.
+ *  - Node boxes per the Introduction: a leaf's box is its own box
+ *    intersected with every clip node on its path to the root; a blend
+ *    node's box is the union of all its descendant leaves (section
+ *    "Parallel bounding boxes": clips first, then unions of clipped boxes;
+ *    descendants are the slice between the open and the close).
+ *  - The union is stored at the close and copied to the open (section "GPU
+ *    implementation of clipping and blending", last paragraph).
+ *
+ * Readings where the paper is silent (each also listed in the design doc):
+ *  - EMPTY = (+inf,+inf,-inf,-inf); a box is kept only if x0<x1 && y0<y1,
+ *    otherwise it becomes EMPTY ("canon").  The whole-plane root clip context
+ *    is INF = (-inf,-inf,+inf,+inf).
+ *  - BEGIN_CLIP's box is canon(own box ∩ enclosing clip context); END_CLIP
+ *    carries the box of its BEGIN_CLIP.  Blends pass the clip context through
+ *    unchanged; only leaves enter unions.
+ *  - Malformed input sets status bits; outputs are then unspecified.
+ *  - Inputs are NaN-free and hold no -0.0.
+ *
+ * The reference gradient (tbo_backward) is not in the paper; its rule is
+ * stated at that function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { LEAF = 0, BEGIN_CLIP = 1, END_CLIP = 2, BEGIN_BLEND = 3, END_BLEND = 4 };
+enum { ST_BAD_KIND = 1u, ST_UNBALANCED = 2u, ST_KIND_MISMATCH = 4u };
+
+typedef struct { float x0, y0, x1, y1; } box4;
+typedef struct { double x0, y0, x1, y1; } box4d;
+
+static float fmx(float a, float b) { return (b > a) ? b : a; }
+static float fmn(float a, float b) { return (b < a) ? b : a; }
+static double dmx(double a, double b) { return (b > a) ? b : a; }
+static double dmn(double a, double b) { return (b < a) ? b : a; }
+
+static box4 b_inf(void) { box4 r = {-INFINITY, -INFINITY, INFINITY, INFINITY}; return r; }
+static box4 b_empty(void) { box4 r = {INFINITY, INFINITY, -INFINITY, -INFINITY}; return r; }
+static box4 b_isect(box4 a, box4 b) {
+    box4 r = {fmx(a.x0, b.x0), fmx(a.y0, b.y0), fmn(a.x1, b.x1), fmn(a.y1, b.y1)};
+    return r;
+}
+static box4 b_union(box4 a, box4 b) {
+    box4 r = {fmn(a.x0, b.x0), fmn(a.y0, b.y0), fmx(a.x1, b.x1), fmx(a.y1, b.y1)};
+    return r;
+}
+static box4 b_canon(box4 a) { return (a.x0 < a.x1 && a.y0 < a.y1) ? a : b_empty(); }
+
+static box4d d_inf(void) { box4d r = {-INFINITY, -INFINITY, INFINITY, INFINITY}; return r; }
+static box4d d_empty(void) { box4d r = {INFINITY, INFINITY, -INFINITY, -INFINITY}; return r; }
+static box4d d_isect(box4d a, box4d b) {
+    box4d r = {dmx(a.x0, b.x0), dmx(a.y0, b.y0), dmn(a.x1, b.x1), dmn(a.y1, b.y1)};
+    return r;
+}
+static box4d d_union(box4d a, box4d b) {
+    box4d r = {dmn(a.x0, b.x0), dmn(a.y0, b.y0), dmx(a.x1, b.x1), dmx(a.y1, b.y1)};
+    return r;
+}
+static box4d d_canon(box4d a) { return (a.x0 < a.x1 && a.y0 < a.y1) ? a : d_empty(); }
+
+/* One stack entry of the sequential walk: the open's index and kind, the
+   clip box its children see, and the blend (union) box accumulated so far. */
+typedef struct {
+    int64_t idx;
+    uint32_t kind;
+    box4 clip, acc;
+} entry;
+
+typedef struct {
+    int64_t idx;
+    uint32_t kind;
+    box4d clip, acc;
+} entryd;
+
+/*
+ * Forward: match, pm (nullable), out (nullable; 4 floats per row).
+ * kind: n values; box: 4n floats (x0,y0,x1,y1 per row).
+ * Returns the status bits.
+ */
+uint32_t tbo_bbox(const uint32_t *kind, const float *box, int64_t n, int32_t *match, int32_t *pm,
+                  float *out) {
+    uint32_t status = 0;
+    entry *S = (entry *)malloc(sizeof(entry) * (size_t)(n + 1));
+    if (!S) return 0xFFFFFFFFu;
+    int64_t sp = 0;
+    S[sp].idx = -1;
+    S[sp].kind = 0xFFFFFFFFu; /* root */
+    S[sp].clip = b_inf();
+    S[sp].acc = b_empty();
+    sp = 1;
+    box4 *o = (box4 *)out;
+    const box4 *bx = (const box4 *)box;
+    for (int64_t i = 0; i < n; ++i) {
+        entry *t = &S[sp - 1];
+        if (pm) pm[i] = (int32_t)t->idx;
+        if (match) match[i] = -1;
+        uint32_t k = kind[i];
+        if (k > 4) {
+            status |= ST_BAD_KIND;
+            if (o) o[i] = b_empty();
+            continue;
+        }
+        if (k == LEAF) {
+            box4 b = box ? b_canon(b_isect(bx[i], t->clip)) : b_empty();
+            if (o) o[i] = b;
+            t->acc = b_union(t->acc, b);
+        } else if (k == BEGIN_CLIP) {
+            box4 c = box ? b_canon(b_isect(bx[i], t->clip)) : b_empty();
+            if (o) o[i] = c;
+            S[sp].idx = i;
+            S[sp].kind = BEGIN_CLIP;
+            S[sp].clip = c;
+            S[sp].acc = b_empty();
+            ++sp;
+        } else if (k == BEGIN_BLEND) {
+            S[sp].idx = i;
+            S[sp].kind = BEGIN_BLEND;
+            S[sp].clip = t->clip;
+            S[sp].acc = b_empty();
+            ++sp;
+        } else { /* END_CLIP or END_BLEND */
+            if (t->idx == -1) {
+                status |= ST_UNBALANCED; /* would pop the root */
+                if (o) o[i] = b_empty();
+                continue;
+            }
+            if ((k == END_CLIP) != (t->kind == BEGIN_CLIP)) status |= ST_KIND_MISMATCH;
+            entry e = S[--sp];
+            if (match) {
+                match[i] = (int32_t)e.idx;
+                match[e.idx] = (int32_t)i;
+            }
+            if (o) {
+                if (e.kind == BEGIN_BLEND) {
+                    o[e.idx] = e.acc;
+                    o[i] = e.acc;
+                } else {
+                    o[i] = o[e.idx];
+                }
+            }
+            S[sp - 1].acc = b_union(S[sp - 1].acc, e.acc);
+        }
+    }
+    if (sp != 1) status |= ST_UNBALANCED;
+    free(S);
+    return status;
+}
+
+/* Matching only (kinds): same walk without boxes. */
+uint32_t tbo_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm) {
+    return tbo_bbox(kind, NULL, n, match, pm, NULL);
+}
+
+/* The same forward walk in fp64 (for finite-difference checks). */
+uint32_t tbo_bbox_f64(const uint32_t *kind, const double *box, int64_t n, double *out) {
+    uint32_t status = 0;
+    entryd *S = (entryd *)malloc(sizeof(entryd) * (size_t)(n + 1));
+    if (!S) return 0xFFFFFFFFu;
+    int64_t sp = 0;
+    S[0].idx = -1;
+    S[0].kind = 0xFFFFFFFFu;
+    S[0].clip = d_inf();
+    S[0].acc = d_empty();
+    sp = 1;
+    box4d *o = (box4d *)out;
+    const box4d *bx = (const box4d *)box;
+    for (int64_t i = 0; i < n; ++i) {
+        entryd *t = &S[sp - 1];
+        uint32_t k = kind[i];
+        if (k > 4) {
+            status |= ST_BAD_KIND;
+            o[i] = d_empty();
+            continue;
+        }
+        if (k == LEAF) {
+            box4d b = d_canon(d_isect(bx[i], t->clip));
+            o[i] = b;
+            t->acc = d_union(t->acc, b);
+        } else if (k == BEGIN_CLIP) {
+            box4d c = d_canon(d_isect(bx[i], t->clip));
+            o[i] = c;
+            S[sp].idx = i;
+            S[sp].kind = BEGIN_CLIP;
+            S[sp].clip = c;
+            S[sp].acc = d_empty();
+            ++sp;
+        } else if (k == BEGIN_BLEND) {
+            S[sp].idx = i;
+            S[sp].kind = BEGIN_BLEND;
+            S[sp].clip = t->clip;
+            S[sp].acc = d_empty();
+            ++sp;
+        } else {
+            if (t->idx == -1) {
+                status |= ST_UNBALANCED;
+                o[i] = d_empty();
+                continue;
+            }
+            if ((k == END_CLIP) != (t->kind == BEGIN_CLIP)) status |= ST_KIND_MISMATCH;
+            entryd e = S[--sp];
+            if (e.kind == BEGIN_BLEND) {
+                o[e.idx] = e.acc;
+                o[i] = e.acc;
+            } else {
+                o[i] = o[e.idx];
+            }
+            S[sp - 1].acc = d_union(S[sp - 1].acc, e.acc);
+        }
+    }
+    if (sp != 1) status |= ST_UNBALANCED;
+    free(S);
+    return status;
+}
+
+/*
+ * Reference gradient (not in the paper).
+ *
+ * Every output coordinate is a max or min of input coordinates, so its
+ * gradient goes to one input coordinate, its "source":
+ *  - LEAF or BEGIN_CLIP row o, coordinate c: the candidates are o itself and
+ *    every BEGIN_CLIP enclosing o; those whose box[.][c] equals out[o][c]
+ *    attain it, and the source is the lowest element index among them.
+ *  - END_CLIP: the source of its BEGIN_CLIP.
+ *  - BEGIN_BLEND / END_BLEND: among the descendant leaves l with out[l] not
+ *    EMPTY and out[l][c] == out[o][c], the sources src(l, c); the lowest
+ *    element index among those.
+ *  - Rows whose out is EMPTY route nothing.
+ * grad_in[src][c] accumulates q(g) = round-half-even(g * 2^32) as an exact
+ * 64-bit integer (order cannot change an integer sum), and is then rounded
+ * once to fp32: grad_in = RNE_fp32(sum) * 2^-32.  Precondition: every
+ * partial sum stays below 2^31 in magnitude.  Rows never attained get 0.
+ *
+ * Written as the definition: every leaf/clip row walks its whole ancestor
+ * chain, every blend row visits every row of its slice.
+ */
+static void sources(const uint32_t *kind, const float *box, int64_t n, const int32_t *match,
+                    const int32_t *pm, const float *out, int64_t *src) {
+    for (int64_t o = 0; o < n; ++o) {
+        for (int c = 0; c < 4; ++c) src[4 * o + c] = -1;
+        uint32_t k = kind[o];
+        if (k != LEAF && k != BEGIN_CLIP) continue;
+        const float *ov = out + 4 * o;
+        if (!(ov[0] < ov[2] && ov[1] < ov[3])) continue; /* EMPTY */
+        for (int c = 0; c < 4; ++c) {
+            int64_t best = (box[4 * o + c] == ov[c]) ? o : -1;
+            /* ancestors come in decreasing index order: the last hit is the lowest */
+            for (int64_t a = pm[o]; a >= 0; a = pm[a])
+                if (kind[a] == BEGIN_CLIP && box[4 * a + c] == ov[c]) best = a;
+            src[4 * o + c] = best;
+        }
+    }
+    for (int64_t o = 0; o < n; ++o)
+        if (kind[o] == END_CLIP && match[o] >= 0)
+            for (int c = 0; c < 4; ++c) src[4 * o + c] = src[4 * match[o] + c];
+    for (int64_t o = 0; o < n; ++o) {
+        if (kind[o] != END_BLEND || match[o] < 0) continue;
+        int64_t op = match[o];
+        const float *ov = out + 4 * o;
+        int64_t best[4] = {-1, -1, -1, -1};
+        if (ov[0] < ov[2] && ov[1] < ov[3]) {
+            for (int64_t l = op + 1; l < o; ++l) {
+                if (kind[l] != LEAF) continue;
+                const float *lv = out + 4 * l;
+                if (!(lv[0] < lv[2] && lv[1] < lv[3])) continue;
+                for (int c = 0; c < 4; ++c) {
+                    if (lv[c] != ov[c]) continue;
+                    int64_t s = src[4 * l + c];
+                    if (best[c] < 0 || s < best[c]) best[c] = s;
+                }
+            }
+        }
+        for (int c = 0; c < 4; ++c) src[4 * o + c] = src[4 * op + c] = best[c];
+    }
+}
+
+/* Sources per output coordinate (4n int64, -1 where nothing routes). */
+uint32_t tbo_sources(const uint32_t *kind, const float *box, int64_t n, int64_t *src) {
+    size_t m = (size_t)(n > 0 ? n : 1);
+    int32_t *match = (int32_t *)malloc(sizeof(int32_t) * m);
+    int32_t *pm = (int32_t *)malloc(sizeof(int32_t) * m);
+    float *out = (float *)malloc(sizeof(float) * 4 * m);
+    if (!match || !pm || !out) return 0xFFFFFFFFu;
+    uint32_t status = tbo_bbox(kind, box, n, match, pm, out);
+    if (!status) sources(kind, box, n, match, pm, out, src);
+    free(match), free(pm), free(out);
+    return status;
+}
+
+uint32_t tbo_backward(const uint32_t *kind, const float *box, const float *grad_out, int64_t n,
+                      float *grad_in) {
+    size_t m = (size_t)(n > 0 ? n : 1);
+    int64_t *src = (int64_t *)malloc(sizeof(int64_t) * 4 * m);
+    int64_t *acc = (int64_t *)calloc(4 * m, sizeof(int64_t));
+    if (!src || !acc) return 0xFFFFFFFFu;
+    uint32_t status = tbo_sources(kind, box, n, src);
+    if (!status) {
+        for (int64_t o = 0; o < n; ++o)
+            for (int c = 0; c < 4; ++c) {
+                int64_t s = src[4 * o + c];
+                if (s < 0) continue;
+                double g = (double)grad_out[4 * o + c] * 4294967296.0; /* exact scaling */
+                acc[4 * s + c] += (int64_t)llrint(g);
+            }
+    }
+    for (int64_t i = 0; i < 4 * n; ++i) grad_in[i] = (float)acc[i] * 0x1p-32f;
+    free(src), free(acc);
+    return status;
+}
