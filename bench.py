@@ -1,0 +1,140 @@
+"""Benchmark: match + bbox forward on the 2^27-element deep-chain scene.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one tb_bbox call (matching, clip intersections, blend unions:
+every kernel of the forward path) over the whole scene, inputs resident in
+HBM.  Prints one JSON line.  The dominant kernel's duration is read live
+with HIP events recorded on the call's stream around its launch.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_FWD = 40  # kind 4 + box 16 in; match 4 + box 16 out
+
+
+class HipEvents:
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        assert self.hip.hipEventCreate(ctypes.byref(e)) == 0
+        return e
+
+    def elapsed_ms(self, a, b):
+        self.hip.hipEventSynchronize(b)
+        ms = ctypes.c_float()
+        assert self.hip.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        return ms.value
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle (single-threaded sequential walk) on a bounded sample of
+    the same workload shape: a deep chain (2^22 opens) around a cap-64 walk of
+    2^23 elements, 2^24 elements in all; repeated up to ~budget_s."""
+    import gen
+    import oracle
+    k, b = gen.chain_around_walk(1 << 22, 1 << 23, 64, gen.SEED_BASE + 102, gen.BOX_NESTED)
+    n = len(k)
+    times = []
+    t_all = time.perf_counter()
+    while time.perf_counter() - t_all < budget_s and len(times) < 8:
+        t0 = time.perf_counter()
+        oracle.bbox(k, b)
+        times.append(time.perf_counter() - t0)
+    best = float(np.median(times))
+    return {"value": round(n / best / 1e9, 4), "unit": "Gelem/s", "cores": 1, "kind": "oracle",
+            "sample": f"deep-chain scene of 2^24 elements (chain 2^22 around a cap-64 walk of 2^23), "
+                      f"median of {len(times)} runs, {best:.3f} s each"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path has no multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+
+    dev = torch.device("cuda:0")
+    c = gen.config(2)
+    n = len(c["kind"])
+    kind = torch.from_numpy(c["kind"].view(np.int32)).to(dev)
+    box = torch.from_numpy(c["box"]).to(dev)
+    del c
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    match = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+
+    for _ in range(args.warmup):
+        tb.tb_bbox(kind, box, match=match, out=out, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0, f"status {int(status.item())}"
+
+    ev = HipEvents()
+    pairs = [(ev.create(), ev.create()) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        tb.lib().tb_profile_events(pairs[k][0], pairs[k][1])
+        tb.tb_bbox(kind, box, match=match, out=out, status=status)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tb.lib().tb_profile_events(None, None)
+    assert int(status.item()) == 0
+    k_ms = float(np.mean([ev.elapsed_ms(a, b) for a, b in pairs]))
+
+    ms_step = wall * 1e3 / args.steps
+    value = n / (ms_step / 1e3) / 1e9
+    achieved = ALG_BYTES_FWD * n / (k_ms / 1e3) / 1e9
+    res = {
+        "metric": "Gelem/s + % HBM peak, match+bbox fwd(+bwd); batched vs per-scene launches",
+        "value": round(value, 3),
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "scene-128M-chain32M", "elements": n,
+                   "structure": "chain of 2^25 alternating clip/blend opens around a cap-64 "
+                                "random walk of 2^26 elements", "op": "tb_bbox forward"},
+        "path_hbm_frac": round(ALG_BYTES_FWD * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": "k_resolve", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "kernel_ms": round(k_ms, 4), "traffic": None},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

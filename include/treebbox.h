@@ -1,0 +1,175 @@
+/*
+ * libtreebbox -- bounding boxes on flattened scene trees, on AMD Instinct
+ * MI355X (gfx950).  C ABI.
+ *
+ * The operations follow R. Levien, "Fast GPU bounding boxes on
+ * tree-structured scenes" (arXiv 2205.11659):
+ *
+ *  - A scene tree is flattened: a node with children is an open element,
+ *    the encoding of its children, then a close element (Introduction,
+ *    "Motivation").  Element kinds are tb_kind below.
+ *  - Matching (section "The parentheses matching problem", Fig. 1): for
+ *    every element, the index on top of the sequential stack before it is
+ *    processed (`pm`; -1 at the root), and the classical partner of every
+ *    open and close (`match`; -1 for leaves), which that section says is
+ *    reconstructed from the former.
+ *  - Boxes (Introduction; section "Parallel bounding boxes"): a leaf's box is
+ *    its own box intersected with every clip node on its path to the root; a
+ *    clip node's box is likewise its own box intersected with its clip
+ *    ancestors; a blend node's box is the union of the clipped boxes of all
+ *    leaves in the slice between its open and its close.  The node box is
+ *    written at both the open and the close element (section "GPU
+ *    implementation of clipping and blending", last paragraph).
+ *
+ * Conventions where the paper is silent:
+ *  - tb_box is (x0, y0, x1, y1), fp32.  A box is non-empty iff x0 < x1 and
+ *    y0 < y1; every empty result is written as EMPTY = (+inf, +inf, -inf,
+ *    -inf).  Inputs must be NaN-free and hold no -0.0.
+ *  - Blend nodes pass their enclosing clip context through unchanged; only
+ *    leaves enter unions.  The box rows of END_CLIP, BEGIN_BLEND and
+ *    END_BLEND inputs are ignored.
+ *  - Results are bit-identical to the sequential walk: matching is integer
+ *    work and fp32 max/min never rounds.
+ *
+ * Memory: every array pointer is a DEVICE pointer owned by the caller.  The
+ * library never allocates; the caller passes a device workspace of at least
+ * tb_workspace_bytes() bytes (contents need not be initialised; the library
+ * overwrites what it reads).  Inputs are read-only; outputs must not alias
+ * inputs or the workspace.  kind and index arrays must be 4-byte aligned,
+ * box arrays 16-byte aligned, the workspace 256-byte aligned.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ * enqueue work on it and return without synchronising.  Two calls that
+ * share a workspace must be ordered on one stream.
+ *
+ * Errors: the return value reports argument errors found on the host before
+ * any work is enqueued (then nothing is enqueued), or TB_ERR_HIP if a launch
+ * fails.  Errors in the data itself are OR-ed as TB_DATA_* bits into the
+ * caller's device status word(s), which the call first clears; when a status
+ * word is non-zero the outputs it covers are unspecified.
+ */
+#ifndef TREEBBOX_H
+#define TREEBBOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TB_LEAF = 0,
+    TB_BEGIN_CLIP = 1,
+    TB_END_CLIP = 2,
+    TB_BEGIN_BLEND = 3,
+    TB_END_BLEND = 4
+} tb_kind;
+
+typedef struct {
+    float x0, y0, x1, y1;
+} tb_box;
+
+typedef enum {
+    TB_OK = 0,
+    TB_ERR_NULL = 1,      /* a required pointer is NULL */
+    TB_ERR_SIZE = 2,      /* n < 0, n >= 2^31, num_scenes < 1, or sizes disagree */
+    TB_ERR_ALIGN = 3,     /* a pointer violates the alignment stated above */
+    TB_ERR_WORKSPACE = 4, /* ws_bytes < tb_workspace_bytes(...) */
+    TB_ERR_ARG = 5,       /* any other invalid argument */
+    TB_ERR_HIP = 6        /* a HIP launch failed */
+} tb_status;
+
+/* Device-side data error bits (OR-ed into the status word). */
+#define TB_DATA_BAD_KIND 0x1u      /* a kind value above 4 */
+#define TB_DATA_UNBALANCED 0x2u    /* a close with no open, or an open never closed */
+#define TB_DATA_KIND_MISMATCH 0x4u /* END_CLIP closing BEGIN_BLEND or vice versa */
+#define TB_DATA_BAD_OFFSETS 0x8u   /* batched: offsets not 0 = o[0] <= ... <= o[S] = total_n */
+
+/* Operation codes for tb_workspace_bytes. */
+#define TB_OP_MATCH 0
+#define TB_OP_BBOX 1
+#define TB_OP_BBOX_BACKWARD 2
+#define TB_OP_BBOX_BATCHED 3
+
+/* Workspace bytes needed by `op` for n elements (num_scenes is used by
+   TB_OP_BBOX_BATCHED only; pass 1 otherwise).  Returns 0 for invalid sizes. */
+size_t tb_workspace_bytes(int op, int64_t n, int64_t num_scenes);
+
+/*
+ * Parentheses matching over element kinds (section "The parentheses matching
+ * problem"; the stronger output of Fig. 1 is `pm`).
+ *   kind   [n]  uint32 tb_kind values                                 (in)
+ *   match  [n]  int32 partner index, -1 for LEAF                      (out)
+ *   pm     [n]  int32 top of the stack before element i, -1 = root    (out, nullable)
+ *   dev_status [1] uint32                                             (out)
+ * n == 0 is valid and enqueues only the status clear.
+ */
+tb_status tb_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                   size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
+ * Matching plus node boxes: clip intersections down the tree and blend
+ * unions up the tree (Introduction; sections "Parallel bounding boxes" and
+ * "GPU implementation of clipping and blending").
+ *   kind    [n]  uint32                                      (in)
+ *   box_in  [n]  tb_box; rows of LEAF and BEGIN_CLIP used    (in)
+ *   match   [n]  int32 partner, -1 for LEAF                  (out, nullable)
+ *   box_out [n]  tb_box node box per element                 (out)
+ *   dev_status [1] uint32                                    (out)
+ */
+tb_status tb_bbox(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
+                  tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
+                  void *stream);
+
+/*
+ * Gradient of tb_bbox's box_out with respect to box_in (not in the paper).
+ * Each output coordinate of a non-EMPTY row routes its gradient to the one
+ * input coordinate that attains it: for LEAF / BEGIN_CLIP / END_CLIP rows,
+ * the lowest element index among the row's own box (END_CLIP: its BEGIN_CLIP)
+ * and its enclosing BEGIN_CLIPs whose coordinate equals the output; for
+ * blend rows, the lowest such index over the descendant leaves whose
+ * non-EMPTY output equals the blend's coordinate.  Contributions are summed
+ * exactly as 64-bit integers on a 2^-32 grid (each g rounded half-to-even to
+ * the grid) and rounded once to fp32, so the result does not depend on
+ * summation order.  Precondition: every partial sum is below 2^31 in
+ * magnitude.
+ *   kind, box_in [n]  as for tb_bbox                         (in)
+ *   grad_out     [n]  tb_box upstream gradient               (in)
+ *   grad_in      [n]  tb_box gradient w.r.t. box_in          (out)
+ *   dev_status   [1]                                         (out)
+ */
+tb_status tb_bbox_backward(const uint32_t *kind, const tb_box *box_in, const tb_box *grad_out,
+                           int64_t n, tb_box *grad_in, void *ws, size_t ws_bytes,
+                           uint32_t *dev_status, void *stream);
+
+/*
+ * Many independent scenes in one call.  Scene s occupies elements
+ * [offsets[s], offsets[s+1]) of the concatenated arrays; matching, clips and
+ * unions never cross a scene boundary, and match indices are scene-local, so
+ * each scene's rows are byte-identical to a tb_bbox call on that scene alone.
+ *   offsets    [num_scenes+1] int64, device, 0 = o[0] <= ... <= o[S] = total_n (in)
+ *   dev_status [num_scenes]   one status word per scene                       (out)
+ * Other arguments as for tb_bbox, with n = total_n.
+ */
+tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int64_t *offsets,
+                          int64_t num_scenes, int64_t total_n, int32_t *match, tb_box *box_out,
+                          void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
+ * Profiling hook: when both are non-NULL, later calls record `before` and
+ * `after` (hipEvent_t handles created by the caller) on the call's stream
+ * immediately around the launch of the main per-partition kernel, so its
+ * duration can be read with hipEventElapsedTime.  Pass NULLs to stop.  Not
+ * thread-safe; meant for benchmarks.
+ */
+void tb_profile_events(void *before, void *after);
+
+/* Static string naming a tb_status value. */
+const char *tb_status_str(tb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREEBBOX_H */

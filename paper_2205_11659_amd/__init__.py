@@ -1,0 +1,187 @@
+"""libtreebbox: bounding boxes on flattened scene trees (arXiv 2205.11659)
+for AMD Instinct MI355X.
+
+Thin binding over the C ABI in include/treebbox.h: arguments are marshalled
+from torch tensors (device memory, current HIP stream); every step of the
+computation runs in the library's HIP kernels.  Importing works without a
+GPU; calling requires the built library and a GPU.
+
+    box_out, match, status = tb_bbox(kind, box)
+    match, pm, status = tb_match(kind)
+    box_out, match, status = tb_bbox_batched(kind, box, offsets)
+    grad_in, status = tb_bbox_backward(kind, box, grad_out)
+    box_out = bbox(kind, box)            # autograd-aware (TreeBBoxFn)
+"""
+import ctypes
+import os
+
+import torch
+
+from ._build import LIB, build  # noqa: F401
+
+LEAF, BEGIN_CLIP, END_CLIP, BEGIN_BLEND, END_BLEND = range(5)
+DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS = 1, 2, 4, 8
+OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED = range(4)
+
+_lib = None
+
+
+class TreeBBoxError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libtreebbox.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise TreeBBoxError(f"libtreebbox.so not built ({LIB}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB)
+        P, I64, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        L.tb_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
+        L.tb_workspace_bytes.restype = SZ
+        L.tb_match.argtypes = [P, I64, P, P, P, SZ, P, P]
+        L.tb_bbox.argtypes = [P, P, I64, P, P, P, SZ, P, P]
+        L.tb_bbox_backward.argtypes = [P, P, P, I64, P, P, SZ, P, P]
+        L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
+        for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched):
+            f.restype = ctypes.c_int
+        L.tb_status_str.argtypes = [ctypes.c_int]
+        L.tb_status_str.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+_ws_cache = {}
+
+
+def workspace(op, n, num_scenes=1, device=None):
+    """A device workspace of at least tb_workspace_bytes(op, n, S) bytes
+    (cached per device; grown on demand)."""
+    need = lib().tb_workspace_bytes(op, n, num_scenes)
+    if need == 0:
+        raise TreeBBoxError(f"invalid size for op {op}: n={n}, scenes={num_scenes}")
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    buf = _ws_cache.get(dev)
+    if buf is None or buf.numel() < need:
+        buf = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        _ws_cache[dev] = buf
+    ptr = buf.data_ptr()
+    pad = (-ptr) % 256
+    return ptr + pad, buf.numel() - pad
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(rc):
+    if rc != 0:
+        raise TreeBBoxError(lib().tb_status_str(rc).decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _as_kind(kind):
+    if kind.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("kind must be int32/uint32")
+    return kind.contiguous()
+
+
+def _as_box(box, n):
+    if box.dtype != torch.float32 or box.shape != (n, 4):
+        raise TypeError("box must be float32 of shape (n, 4)")
+    return box.contiguous()
+
+
+def tb_match(kind, pm=True):
+    """Matching only: returns (match int32[n], pm int32[n] or None, status int32[1])."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    dev = kind.device
+    match = torch.empty(n, dtype=torch.int32, device=dev)
+    pmo = torch.empty(n, dtype=torch.int32, device=dev) if pm else None
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    ws, wsb = workspace(OP_MATCH, n, 1, dev)
+    _check(lib().tb_match(_ptr(kind), n, _ptr(match), _ptr(pmo), ctypes.c_void_p(ws), wsb,
+                          _ptr(status), _stream()))
+    return match, pmo, status
+
+
+def tb_bbox(kind, box, match=True, out=None, status=None):
+    """Forward: returns (box_out float32[n,4], match int32[n] or None, status int32[1]).
+    `match` may be True/False or a preallocated int32 tensor; `out` and
+    `status` may be preallocated too."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    box = _as_box(box, n)
+    dev = kind.device
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev) if out is None else out
+    if isinstance(match, torch.Tensor):
+        m = match
+    else:
+        m = torch.empty(n, dtype=torch.int32, device=dev) if match else None
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    ws, wsb = workspace(OP_BBOX, n, 1, dev)
+    _check(lib().tb_bbox(_ptr(kind), _ptr(box), n, _ptr(m), _ptr(out), ctypes.c_void_p(ws), wsb,
+                         _ptr(status), _stream()))
+    return out, m, status
+
+
+def tb_bbox_batched(kind, box, offsets, match=True):
+    """Ragged batch: offsets int64[S+1] on the device.  Returns
+    (box_out, match (scene-local) or None, status int32[S])."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    box = _as_box(box, n)
+    if offsets.dtype != torch.int64:
+        raise TypeError("offsets must be int64")
+    offsets = offsets.contiguous()
+    S = offsets.numel() - 1
+    dev = kind.device
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    m = torch.empty(n, dtype=torch.int32, device=dev) if match else None
+    status = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    ws, wsb = workspace(OP_BBOX_BATCHED, n, S, dev)
+    _check(lib().tb_bbox_batched(_ptr(kind), _ptr(box), _ptr(offsets), S, n, _ptr(m), _ptr(out),
+                                 ctypes.c_void_p(ws), wsb, _ptr(status), _stream()))
+    return out, m, status
+
+
+def tb_bbox_backward(kind, box, grad_out):
+    """Gradient of tb_bbox's box output w.r.t. box: returns (grad_in, status)."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    box = _as_box(box, n)
+    grad_out = _as_box(grad_out, n)
+    dev = kind.device
+    gin = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    ws, wsb = workspace(OP_BBOX_BACKWARD, n, 1, dev)
+    _check(lib().tb_bbox_backward(_ptr(kind), _ptr(box), _ptr(grad_out), n, _ptr(gin),
+                                  ctypes.c_void_p(ws), wsb, _ptr(status), _stream()))
+    return gin, status
+
+
+class TreeBBoxFn(torch.autograd.Function):
+    """box_out = TreeBBoxFn.apply(kind, box); match is returned non-differentiable."""
+
+    @staticmethod
+    def forward(ctx, kind, box):
+        out, match, status = tb_bbox(kind, box)
+        ctx.save_for_backward(kind, box)
+        ctx.mark_non_differentiable(match, status)
+        return out, match, status
+
+    @staticmethod
+    def backward(ctx, g_out, _g_match, _g_status):
+        kind, box = ctx.saved_tensors
+        gin, _ = tb_bbox_backward(kind, box, g_out.contiguous())
+        return None, gin
+
+
+def bbox(kind, box):
+    out, _, _ = TreeBBoxFn.apply(kind, box)
+    return out

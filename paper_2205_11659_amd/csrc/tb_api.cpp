@@ -1,0 +1,120 @@
+// libtreebbox C ABI (include/treebbox.h): argument checks on the host, then
+// the kernel pipelines.  No allocation happens here: the caller's workspace
+// holds every intermediate array.
+#include <hip/hip_runtime.h>
+
+#include "../../include/treebbox.h"
+#include "tb_forward.h"
+
+namespace {
+
+constexpr int64_t MAX_N = (int64_t)1 << 31;
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t ws_bytes_for(int op, int64_t n, int64_t S) {
+    if (n < 0 || n >= MAX_N) return 0;
+    switch (op) {
+    case TB_OP_MATCH:
+    case TB_OP_BBOX:
+        return tb::fwd_layout(n, 1).total;
+    case TB_OP_BBOX_BATCHED:
+        if (S < 1 || S >= MAX_N) return 0;
+        return tb::fwd_layout(n, S).total;
+    case TB_OP_BBOX_BACKWARD:
+        return 0;  // not available in this build
+    default:
+        return 0;
+    }
+}
+
+tb_status check_common(const void *kind, int64_t n, const void *ws, size_t ws_bytes, int op,
+                       int64_t S) {
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!ws) return TB_ERR_NULL;
+    if (n > 0 && !kind) return TB_ERR_NULL;
+    if (!aligned(ws, 256) || (kind && !aligned(kind, 4))) return TB_ERR_ALIGN;
+    size_t need = ws_bytes_for(op, n, S);
+    if (need == 0 || ws_bytes < need) return TB_ERR_WORKSPACE;
+    return TB_OK;
+}
+
+tb_status launched(hipError_t e) { return e == hipSuccess ? TB_OK : TB_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t tb_workspace_bytes(int op, int64_t n, int64_t num_scenes) {
+    return ws_bytes_for(op, n, num_scenes);
+}
+
+tb_status tb_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                   size_t ws_bytes, uint32_t *dev_status, void *stream) {
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!dev_status || (n > 0 && !match)) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (match && !aligned(match, 4)) || (pm && !aligned(pm, 4)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(kind, n, ws, ws_bytes, TB_OP_MATCH, 1);
+    if (c != TB_OK) return c;
+    return launched(tb::fwd_run(false, kind, nullptr, n, nullptr, 1, match, pm, nullptr, ws,
+                                dev_status, (hipStream_t)stream));
+}
+
+tb_status tb_bbox(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
+                  tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
+                  void *stream) {
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!dev_status || (n > 0 && (!box_in || !box_out))) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (box_in && !aligned(box_in, 16)) ||
+        (box_out && !aligned(box_out, 16)) || (match && !aligned(match, 4)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(kind, n, ws, ws_bytes, TB_OP_BBOX, 1);
+    if (c != TB_OK) return c;
+    return launched(tb::fwd_run(true, kind, (const float4 *)box_in, n, nullptr, 1, match, nullptr,
+                                (float4 *)box_out, ws, dev_status, (hipStream_t)stream));
+}
+
+tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int64_t *offsets,
+                          int64_t num_scenes, int64_t total_n, int32_t *match, tb_box *box_out,
+                          void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream) {
+    if (total_n < 0 || total_n >= MAX_N || num_scenes < 1 || num_scenes >= MAX_N)
+        return TB_ERR_SIZE;
+    if (!dev_status || !offsets || (total_n > 0 && (!box_in || !box_out))) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || !aligned(offsets, 8) || (box_in && !aligned(box_in, 16)) ||
+        (box_out && !aligned(box_out, 16)) || (match && !aligned(match, 4)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(kind, total_n, ws, ws_bytes, TB_OP_BBOX_BATCHED, num_scenes);
+    if (c != TB_OK) return c;
+    return launched(tb::fwd_run(true, kind, (const float4 *)box_in, total_n, offsets, num_scenes,
+                                match, nullptr, (float4 *)box_out, ws, dev_status,
+                                (hipStream_t)stream));
+}
+
+tb_status tb_bbox_backward(const uint32_t *kind, const tb_box *box_in, const tb_box *grad_out,
+                           int64_t n, tb_box *grad_in, void *ws, size_t ws_bytes,
+                           uint32_t *dev_status, void *stream) {
+    (void)kind, (void)box_in, (void)grad_out, (void)n, (void)grad_in, (void)ws, (void)ws_bytes,
+        (void)dev_status, (void)stream;
+    return TB_ERR_ARG;
+}
+
+void tb_profile_events(void *before, void *after) {
+    tb::g_prof_before = (hipEvent_t)before;
+    tb::g_prof_after = (hipEvent_t)after;
+}
+
+const char *tb_status_str(tb_status s) {
+    switch (s) {
+    case TB_OK: return "TB_OK";
+    case TB_ERR_NULL: return "TB_ERR_NULL: a required pointer is NULL";
+    case TB_ERR_SIZE: return "TB_ERR_SIZE: size out of range";
+    case TB_ERR_ALIGN: return "TB_ERR_ALIGN: misaligned pointer";
+    case TB_ERR_WORKSPACE: return "TB_ERR_WORKSPACE: workspace too small";
+    case TB_ERR_ARG: return "TB_ERR_ARG: invalid argument";
+    case TB_ERR_HIP: return "TB_ERR_HIP: HIP launch failed";
+    }
+    return "unknown tb_status";
+}
+
+}  // extern "C"

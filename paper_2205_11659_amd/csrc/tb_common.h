@@ -1,0 +1,280 @@
+// Device-side building blocks shared by the libtreebbox kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tb {
+
+// Partition geometry: one workgroup of W threads handles T = W*K consecutive
+// elements; every thread walks K consecutive elements sequentially.
+constexpr int WAVE = 64;
+constexpr int W = 256;
+constexpr int K = 4;
+constexpr int T = W * K;
+constexpr int NWAVE = W / WAVE;
+constexpr int32_t SENT = INT32_MIN;  // "segment reset": below every real level
+constexpr int RUNCAP = 64;           // owner runs gathered per round
+constexpr int UB = 256;              // partitions per union block
+
+enum : uint32_t { LEAF = 0, BCLIP = 1, ECLIP = 2, BBLEND = 3, EBLEND = 4 };
+enum : uint32_t { ST_BAD_KIND = 1u, ST_UNBAL = 2u, ST_MISMATCH = 4u, ST_BAD_OFF = 8u };
+constexpr uint32_t BLEND_BIT = 0x80000000u;  // U-slot index word: open is a blend
+
+__device__ __forceinline__ bool is_open(uint32_t k) { return k == BCLIP || k == BBLEND; }
+__device__ __forceinline__ bool is_close(uint32_t k) { return k == ECLIP || k == EBLEND; }
+
+// ------------------------------------------------------------------ boxes
+struct Box {
+    float x0, y0, x1, y1;
+};
+
+__device__ __forceinline__ Box box_inf() { return {-INFINITY, -INFINITY, INFINITY, INFINITY}; }
+__device__ __forceinline__ Box box_empty() { return {INFINITY, INFINITY, -INFINITY, -INFINITY}; }
+// Intersection and union are exact (max/min never round).
+__device__ __forceinline__ Box isect(Box a, Box b) {
+    return {fmaxf(a.x0, b.x0), fmaxf(a.y0, b.y0), fminf(a.x1, b.x1), fminf(a.y1, b.y1)};
+}
+__device__ __forceinline__ Box unite(Box a, Box b) {
+    return {fminf(a.x0, b.x0), fminf(a.y0, b.y0), fmaxf(a.x1, b.x1), fmaxf(a.y1, b.y1)};
+}
+__device__ __forceinline__ Box canon(Box a) {
+    return (a.x0 < a.x1 && a.y0 < a.y1) ? a : box_empty();
+}
+__device__ __forceinline__ Box ld_box(const float4 *p, int64_t i) {
+    float4 v = p[i];
+    return {v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void st_box(float4 *p, int64_t i, Box b) {
+    p[i] = make_float4(b.x0, b.y0, b.x1, b.y1);
+}
+
+// ---------------------------------------------------------- wave shuffles
+__device__ __forceinline__ int shfl_up(int v, int d) { return __shfl_up(v, d, WAVE); }
+__device__ __forceinline__ float shfl_up(float v, int d) { return __shfl_up(v, d, WAVE); }
+__device__ __forceinline__ Box shfl_up(Box v, int d) {
+    return {shfl_up(v.x0, d), shfl_up(v.y0, d), shfl_up(v.x1, d), shfl_up(v.y1, d)};
+}
+
+// Segmented sum: (r, v) with r = "a reset occurs in this range"; a reset
+// discards everything to its left.
+struct Seg {
+    int r, v;
+};
+__device__ __forceinline__ Seg shfl_up(Seg s, int d) { return {shfl_up(s.r, d), shfl_up(s.v, d)}; }
+struct SegOp {
+    __device__ Seg operator()(Seg x, Seg y) const { return y.r ? y : Seg{x.r, x.v + y.v}; }
+};
+struct MinOp {
+    __device__ int operator()(int a, int b) const { return a < b ? a : b; }
+};
+struct AddOp {
+    __device__ int operator()(int a, int b) const { return a + b; }
+};
+struct IsectOp {
+    __device__ Box operator()(Box a, Box b) const { return isect(a, b); }
+};
+struct UniteOp {
+    __device__ Box operator()(Box a, Box b) const { return unite(a, b); }
+};
+
+template <class V, class Op>
+__device__ __forceinline__ V wave_incl_scan(V v, Op op) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        V u = shfl_up(v, o);
+        if (lane >= o) v = op(u, v);
+    }
+    return v;
+}
+
+// Exclusive scan over the NW*64 threads of a workgroup; `sh` holds NW values.
+// Also returns the workgroup total.  Contains two barriers.
+template <int NW, class V, class Op>
+__device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *total) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    V inc = wave_incl_scan(v, op);
+    if (lane == WAVE - 1) sh[wid] = inc;
+    __syncthreads();
+    V pre = ident, tot = ident;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wid) pre = op(pre, sh[w]);
+        tot = op(tot, sh[w]);
+    }
+    V ex = shfl_up(inc, 1);
+    if (lane == 0) ex = ident;
+    *total = tot;
+    __syncthreads();
+    return op(pre, ex);
+}
+
+// ----------------------------------------------------------- small helpers
+__device__ __forceinline__ int msb32(uint32_t x) { return 31 - __clz(x); }
+
+// position of the j-th (0-based) set bit of a K-bit mask, or -1
+__device__ __forceinline__ int nth_bit(uint32_t mask, int j) {
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+        if ((mask >> p) & 1u) {
+            if (j == 0) return p;
+            --j;
+        }
+    }
+    return -1;
+}
+
+template <class V>
+__device__ __forceinline__ V pick(const V (&a)[K], int i) {
+    V r = a[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j)
+        if (i == j) r = a[j];
+    return r;
+}
+
+// lower_bound over off[0..cnt): first index with off[idx] >= x
+__device__ __forceinline__ int64_t lower_bound64(const int64_t *off, int64_t cnt, int64_t x) {
+    int64_t lo = 0, hi = cnt;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (off[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// scene holding element i: last s with off[s] <= i, clamped to [0, S-1]
+__device__ __forceinline__ int64_t scene_of(const int64_t *off, int64_t S, int64_t i) {
+    if (!off) return 0;
+    int64_t lo = 0, hi = S + 1;  // first index with off[idx] > i
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int64_t s = lo - 1;
+    return s < 0 ? 0 : (s >= S ? S - 1 : s);
+}
+
+// Scene starts inside [g0, g0+K) as a bit mask (bit j: element g0+j starts a
+// scene).  Without offsets the only start is element 0.
+__device__ __forceinline__ uint32_t reset_mask(const int64_t *off, int64_t S, int64_t g0) {
+    if (!off) return g0 == 0 ? 1u : 0u;
+    uint32_t r = 0;
+    for (int64_t s = lower_bound64(off, S + 1, g0); s <= S; ++s) {
+        int64_t o = off[s];
+        if (o >= g0 + K) break;
+        if (o >= g0) r |= 1u << (o - g0);
+    }
+    return r;
+}
+
+__device__ __forceinline__ void flag(uint32_t *status, const int64_t *off, int64_t S, int64_t i,
+                                     uint32_t bits) {
+    atomicOr(status + scene_of(off, S, i), bits);
+}
+
+// Loads K kinds of one thread; elements at or past n read as LEAF.
+__device__ __forceinline__ void load_kinds(const uint32_t *kind, int64_t n, int64_t g0,
+                                           uint32_t (&ks)[K]) {
+    if (g0 + K <= n) {
+        uint4 v = *reinterpret_cast<const uint4 *>(kind + g0);
+        ks[0] = v.x, ks[1] = v.y, ks[2] = v.z, ks[3] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) ks[j] = (g0 + j < n) ? kind[g0 + j] : LEAF;
+    }
+}
+
+// Per-thread sequential walk over K kinds with a bitmask stack of local
+// opens (the top is the highest set bit).  Returns the pops of the incoming
+// stack before the first scene start (a), the mask of unmatched opens after
+// the last scene start, and whether a scene starts in this thread.
+struct Walk {
+    int a;
+    uint32_t umask;
+    bool rs;
+};
+__device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[K], uint32_t rm) {
+    uint32_t mask = 0;
+    int a = 0;
+    bool rs = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if ((rm >> j) & 1u) {
+            mask = 0;
+            rs = true;
+        }
+        uint32_t k = ks[j];
+        if (is_open(k))
+            mask |= 1u << j;
+        else if (is_close(k)) {
+            if (mask)
+                mask &= ~(1u << msb32(mask));
+            else if (!rs)
+                ++a;
+        }
+    }
+    return {a, mask, rs};
+}
+
+// ------------------------------------------------- LDS min tree over W ints
+// mt[W + i] = leaf i; mt[x] = min(mt[2x], mt[2x+1]) for 1 <= x < W.
+__device__ __forceinline__ void mintree_build(int *mt) {
+    for (int w = W / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            int x = w + threadIdx.x;
+            int a = mt[2 * x], b = mt[2 * x + 1];
+            mt[x] = a < b ? a : b;
+        }
+        __syncthreads();
+    }
+}
+
+// rightmost leaf s < t with leaf value < v, or -1
+__device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int64_t v) {
+    int x = W + t;
+    while (x > 1) {
+        if ((x & 1) && (int64_t)mt[x - 1] < v) {
+            x = x - 1;
+            while (x < W) x = ((int64_t)mt[2 * x + 1] < v) ? 2 * x + 1 : 2 * x;
+            return x - W;
+        }
+        x >>= 1;
+    }
+    return -1;
+}
+
+// min over leaves [lo, hi] (INT32_MAX if empty)
+__device__ __forceinline__ int mintree_range_min(const int *mt, int lo, int hi) {
+    int r = INT32_MAX;
+    if (lo > hi) return r;
+    int l = lo + W, h = hi + W + 1;
+    while (l < h) {
+        if (l & 1) r = min(r, mt[l++]);
+        if (h & 1) r = min(r, mt[--h]);
+        l >>= 1, h >>= 1;
+    }
+    return r;
+}
+
+// union over leaves [lo, hi] of an LDS segment tree of boxes (EMPTY if empty)
+__device__ __forceinline__ Box uniontree_range(const Box *ut, int lo, int hi) {
+    Box r = box_empty();
+    if (lo > hi) return r;
+    int l = lo + W, h = hi + W + 1;
+    while (l < h) {
+        if (l & 1) r = unite(r, ut[l++]);
+        if (h & 1) r = unite(r, ut[--h]);
+        l >>= 1, h >>= 1;
+    }
+    return r;
+}
+
+}  // namespace tb

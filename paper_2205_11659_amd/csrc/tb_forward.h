@@ -1,0 +1,31 @@
+// Host-side entry into the forward kernels (tb_forward.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tb {
+
+// Byte offsets of the forward pipeline's arrays inside the caller's workspace.
+struct FwdLayout {
+    int64_t M, Mp, nb;
+    int levels;
+    size_t pinfo, part, mtree, jptr0, jptr1, jval0, jval1;
+    size_t U_idx, U_cum, U_suf, cr_slot, cr_c, cr_pre;
+    size_t ptot, upre, usuf, sp, status;
+    size_t total;
+};
+
+FwdLayout fwd_layout(int64_t n, int64_t S);
+
+// Enqueue the forward pipeline.  boxes=false computes matching only.
+// off == nullptr means one scene.  status may be nullptr (workspace word).
+hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t n,
+                   const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
+                   void *ws, uint32_t *status, hipStream_t st);
+
+// Events recorded around the main per-partition kernel (nullptr = off).
+extern hipEvent_t g_prof_before, g_prof_after;
+
+}  // namespace tb
