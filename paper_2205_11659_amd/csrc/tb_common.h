@@ -14,7 +14,7 @@ constexpr int K = 4;
 constexpr int T = W * K;
 constexpr int NWAVE = W / WAVE;
 constexpr int32_t SENT = INT32_MIN;  // "segment reset": below every real level
-constexpr int RUNCAP = 64;           // owner runs gathered per round
+constexpr int RMAX = 32;             // owner runs stored per partition
 constexpr int UB = 256;              // partitions per union block
 
 enum : uint32_t { LEAF = 0, BCLIP = 1, ECLIP = 2, BBLEND = 3, EBLEND = 4 };
@@ -54,6 +54,11 @@ __device__ __forceinline__ int shfl_up(int v, int d) { return __shfl_up(v, d, WA
 __device__ __forceinline__ float shfl_up(float v, int d) { return __shfl_up(v, d, WAVE); }
 __device__ __forceinline__ Box shfl_up(Box v, int d) {
     return {shfl_up(v.x0, d), shfl_up(v.y0, d), shfl_up(v.x1, d), shfl_up(v.y1, d)};
+}
+__device__ __forceinline__ int shfl_xor(int v, int m) { return __shfl_xor(v, m, WAVE); }
+__device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, WAVE); }
+__device__ __forceinline__ Box shfl_xor(Box v, int m) {
+    return {shfl_xor(v.x0, m), shfl_xor(v.y0, m), shfl_xor(v.x1, m), shfl_xor(v.y1, m)};
 }
 
 // Segmented sum: (r, v) with r = "a reset occurs in this range"; a reset
@@ -125,11 +130,11 @@ __device__ __forceinline__ int nth_bit(uint32_t mask, int j) {
     return -1;
 }
 
-template <class V>
-__device__ __forceinline__ V pick(const V (&a)[K], int i) {
+template <class V, int N>
+__device__ __forceinline__ V pick(const V (&a)[N], int i) {
     V r = a[0];
 #pragma unroll
-    for (int j = 1; j < K; ++j)
+    for (int j = 1; j < N; ++j)
         if (i == j) r = a[j];
     return r;
 }
@@ -226,15 +231,36 @@ __device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[K], uint32_t rm)
 
 // ------------------------------------------------- LDS min tree over W ints
 // mt[W + i] = leaf i; mt[x] = min(mt[2x], mt[2x+1]) for 1 <= x < W.
-__device__ __forceinline__ void mintree_build(int *mt) {
-    for (int w = W / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            int x = w + threadIdx.x;
-            int a = mt[2 * x], b = mt[2 * x + 1];
-            mt[x] = a < b ? a : b;
-        }
-        __syncthreads();
+// Thread t supplies leaf t.  The levels inside a wave are formed with
+// butterfly shuffles; only the NWAVE-wide top needs LDS.  Two barriers.
+__device__ __forceinline__ void mintree_build(int *mt, int v) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1);
+    mt[W + t] = v;
+#pragma unroll
+    for (int l = 1; (1 << l) <= WAVE; ++l) {
+        const int o = shfl_xor(v, 1 << (l - 1));
+        v = o < v ? o : v;
+        if ((lane & ((1 << l) - 1)) == 0) mt[(W + t) >> l] = v;
     }
+    __syncthreads();
+    if (t == 0)
+        for (int x = NWAVE - 1; x >= 1; --x) mt[x] = min(mt[2 * x], mt[2 * x + 1]);
+    __syncthreads();
+}
+
+// The same for a union tree of boxes.
+__device__ __forceinline__ void uniontree_build(Box *ut, Box v) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1);
+    ut[W + t] = v;
+#pragma unroll
+    for (int l = 1; (1 << l) <= WAVE; ++l) {
+        v = unite(v, shfl_xor(v, 1 << (l - 1)));
+        if ((lane & ((1 << l) - 1)) == 0) ut[(W + t) >> l] = v;
+    }
+    __syncthreads();
+    if (t == 0)
+        for (int x = NWAVE - 1; x >= 1; --x) ut[x] = unite(ut[2 * x], ut[2 * x + 1]);
+    __syncthreads();
 }
 
 // rightmost leaf s < t with leaf value < v, or -1

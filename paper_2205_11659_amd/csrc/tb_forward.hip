@@ -92,9 +92,7 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
 
     // an unmatched open at level L survives the partition unless a later
     // thread's lowest level is below L
-    mt[W + t] = cm;
-    __syncthreads();
-    mintree_build(mt);
+    mintree_build(mt, cm);
     const int sufmin = mintree_range_min(mt, t + 1, W - 1);
     int ns = 0;
     if ((int64_t)sufmin > (int64_t)base) ns = (int)min((int64_t)b, (int64_t)sufmin - base);
@@ -238,32 +236,110 @@ __global__ void k_jump(const int32_t *__restrict__ ptr_in, const float4 *__restr
     st_box(val_out, P, v);
 }
 
+// ---------------------------------------------------------------- k_runs
+// Owner runs of each partition's incoming levels [max(preM,1), dP]: walking
+// the owner links from P-1, each owner R holds a contiguous range of levels
+// (its surviving opens).  One thread per partition; many chains are walked
+// at once, which hides the dependent loads.  Up to RMAX runs are stored;
+// head = {count, next owner, next top level, complete}.
+__global__ void k_runs(const int4 *__restrict__ pinfo, const int4 *__restrict__ part, int64_t M,
+                       int4 *__restrict__ runs, int4 *__restrict__ rhead) {
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= M) return;
+    const int64_t dP = part[P].x;
+    const int64_t preM = dP - pinfo[P].x;
+    const int64_t need_lo = preM > 1 ? preM : 1;
+    int64_t R = P - 1, hi = dP;
+    int nr = 0;
+    while (nr < RMAX && R >= 0 && hi >= need_lo) {
+        const int4 pr = part[R];
+        const int64_t from = max((int64_t)pr.z + 1, need_lo);
+        if (from <= hi) runs[P * RMAX + nr++] = make_int4((int)R, (int)from, (int)hi, pr.z);
+        if (pr.y == SENT) {
+            R = -1;
+            break;
+        }
+        hi = min(hi, (int64_t)pr.y);
+        R = pr.w;
+    }
+    const bool complete = !(R >= 0 && hi >= need_lo);
+    rhead[P] = make_int4(nr, (int)R, (int)hi, complete ? 1 : 0);
+}
+
 // ------------------------------------------------------------- k_resolve
 // Stack entry at some level as seen from the start of a thread.
 struct Ent {
-    int64_t idx;   // element index of the open, -1 = root
-    Box ctx;       // clip context of the entry (its children's context)
-    int kind;      // kind of the open (BCLIP/BBLEND), -1 for root
-    int own;       // owning thread in this partition, or -1
-    int pos;       // position of the open in the owning thread
-    int slot;      // global U slot when owned by an earlier partition, else -1
+    int64_t idx;  // element index of the open, -1 = root
+    Box ctx;      // clip context of the entry (its children's context)
+    int kind;     // kind of the open (BCLIP/BBLEND), -1 for root
+    int own;      // owning thread in this partition, or -1
+    int pos;      // position of the open in the owning thread
+    int slot;     // global U slot when owned by an earlier partition, else -1
 };
+
+__device__ __forceinline__ Ent ent_root() { return Ent{-1, box_inf(), -1, -1, -1, -1}; }
+
+// Owner run holding level L (runs cover disjoint level ranges, highest
+// first): binary search; -1 if L lies below the stored runs.
+__device__ __forceinline__ int find_run(const int4 *runs, int nruns, int64_t L) {
+    int lo = 0, hi = nruns - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int4 r = runs[mid];
+        if (L > r.z)
+            hi = mid - 1;
+        else if (L < r.y)
+            lo = mid + 1;
+        else
+            return mid;
+    }
+    return -1;
+}
+
+// Slot of the entry at level L >= 1 held by an earlier partition (global U
+// slot), or -1.  Continues the owner walk when the stored runs end early.
+__device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 head,
+                                 const int4 *__restrict__ part, int64_t *owner) {
+    int64_t R = -1, base = 0;
+    const int r = find_run(runs, nruns, L);
+    if (r >= 0) {
+        R = runs[r].x;
+        base = runs[r].w;
+    } else if (!head.w) {
+        int64_t RR = head.y, hi = head.z;
+        while (RR >= 0 && hi >= L) {
+            const int4 pr = part[RR];
+            if (L > pr.z && L <= hi) {
+                R = RR;
+                base = pr.z;
+                break;
+            }
+            if (pr.y == SENT) break;
+            hi = min(hi, (int64_t)pr.y);
+            RR = pr.w;
+        }
+    }
+    *owner = R;
+    if (R < 0 || L - base - 1 < 0 || L - base - 1 >= T) return -1;
+    return R * T + (L - base - 1);
+}
 
 template <bool BOXES>
 struct ResolveSmem {
-    int inc_slot[T + 1];
+    int4 runs[RMAX];
+    // incoming levels [preM, dP], entry x = level preM + x: the open's index
+    // (| BLEND_BIT) or -1 for the root, and its clip context.  After the walk
+    // the context array is reused as the union tree over threads.
+    int inc_idx[T + 1];
     Box inc_ctx[BOXES ? T + 1 : 1];
     Box ucum[BOXES ? T : 1];  // local clip prefix of thread U entries; later suffix unions
+    Box jval[BOXES ? W : 1];  // clip context at each thread's base level
     uint8_t tkind[T];
     int tcm[W];
     int tbase[W];
     uint8_t tum[W];
     int mt[2 * W];
-    Box jval[BOXES ? W : 1];
     int jptr[W];
-    Box ut[BOXES ? 2 * W : 1];
-    int4 runs[RUNCAP];
-    int nruns, done;
     Seg sh_seg[NWAVE];
 };
 
@@ -271,23 +347,26 @@ template <bool BOXES>
 __global__ __launch_bounds__(W) void k_resolve(
     const uint32_t *__restrict__ kind, const float4 *__restrict__ box, int64_t n,
     const int64_t *__restrict__ off, int64_t S, const int4 *__restrict__ pinfo,
-    const int4 *__restrict__ part, const float4 *__restrict__ base_ctx,
+    const int4 *__restrict__ part, const int4 *__restrict__ runs_g,
+    const int4 *__restrict__ rhead_g, const float4 *__restrict__ base_ctx,
     const int32_t *__restrict__ U_idx, const float4 *__restrict__ U_cum,
     float4 *__restrict__ U_suf, int32_t *__restrict__ cr_slot, int32_t *__restrict__ cr_c,
     float4 *__restrict__ cr_pre, float4 *__restrict__ ptot, int32_t *__restrict__ match,
     int32_t *__restrict__ pm, float4 *__restrict__ out, uint32_t *__restrict__ status) {
     __shared__ ResolveSmem<BOXES> sm;
-    const int t = threadIdx.x;
+    Box *ut = sm.inc_ctx;  // valid once the walk is over
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
     const int64_t P = blockIdx.x;
     const int64_t p0 = P * T;
     const int64_t g0 = p0 + (int64_t)t * K;
     const int4 myp = part[P];
-    const int4 myi = pinfo[P];
     const int64_t dP = myp.x;
-    const int aP = myi.x;
-    const int64_t preM = dP - aP;  // lowest incoming level this partition reads
+    const int aP = pinfo[P].x;
+    const int64_t preM = dP - aP;  // lowest incoming level any element here can see
+    const int4 head = rhead_g[P];
+    const int nruns = head.x;
 
-    // ---- loads (issued first; the chain walk below overlaps them)
+    // ---- loads: inputs, owner runs
     uint32_t kr[K], ks[K];
     load_kinds(kind, n, g0, kr);
     Box bx[K];
@@ -295,56 +374,28 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
         for (int j = 0; j < K; ++j) bx[j] = (g0 + j < n) ? ld_box(box, g0 + j) : box_empty();
     }
+    if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
     for (int j = 0; j < K; ++j) ks[j] = kr[j] > 4u ? LEAF : kr[j];
     const uint32_t rm = reset_mask(off, S, g0);
-
-    // ---- incoming stack levels [preM, dP]: default root
-    for (int x = t; x <= aP; x += W) {
-        sm.inc_slot[x] = -1;
-        if (BOXES) sm.inc_ctx[x] = box_inf();
-    }
-    if (t == 0) sm.done = 0;
     __syncthreads();
-    {
-        int64_t R = P - 1, hi = dP;
-        const int64_t need_lo = preM > 1 ? preM : 1;
-        while (true) {
-            if (t == 0) {
-                int nr = 0;
-                while (nr < RUNCAP && R >= 0 && hi >= need_lo) {
-                    const int4 pr = part[R];
-                    const int64_t from = max((int64_t)pr.z + 1, need_lo);
-                    if (from <= hi) sm.runs[nr++] = make_int4((int)R, (int)from, (int)hi, pr.z);
-                    if (pr.y == SENT) {
-                        R = -1;
-                        break;
-                    }
-                    hi = min(hi, (int64_t)pr.y);
-                    R = pr.w;
-                }
-                sm.nruns = nr;
-                sm.done = !(R >= 0 && hi >= need_lo);
-            }
-            __syncthreads();
-            const int nr = sm.nruns;
-            for (int r = 0; r < nr; ++r) {
-                const int4 run = sm.runs[r];
-                const int64_t RR = run.x;
-                const int bR = pinfo[RR].y;
-                const Box bc = BOXES ? ld_box(base_ctx, RR) : box_inf();
-                for (int64_t L = (int64_t)run.y + t; L <= run.z; L += W) {
-                    const int64_t j = L - run.w - 1;
-                    const int64_t x = L - preM;
-                    if (j < 0 || j >= bR || x < 0 || x > aP) continue;
-                    sm.inc_slot[x] = (int)(RR * T + j);
-                    if (BOXES) sm.inc_ctx[x] = isect(ld_box(U_cum, RR * T + j), bc);
-                }
-            }
-            const int dn = sm.done;
-            __syncthreads();
-            if (dn) break;
-        }
+
+    // ---- gather the incoming levels [preM, dP] (issued now, stored later)
+    constexpr int NG = (T + W) / W;  // entries per thread
+    int g_idx[NG];
+    Box g_ctx[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        g_idx[q] = -1;
+        g_ctx[q] = box_inf();
+        const int x = t + q * W;
+        const int64_t L = preM + x;
+        if (x > aP || L < 1) continue;
+        int64_t R;
+        const int64_t slot = incoming_slot(L, sm.runs, nruns, head, part, &R);
+        if (slot < 0) continue;
+        g_idx[q] = U_idx[slot];
+        if (BOXES) g_ctx[q] = isect(ld_box(U_cum, slot), ld_box(base_ctx, R));
     }
 
     // ---- per-thread walk and thread-level depths
@@ -360,7 +411,6 @@ __global__ __launch_bounds__(W) void k_resolve(
     sm.tcm[t] = cm;
     sm.tbase[t] = base;
     sm.tum[t] = (uint8_t)wk.umask;
-    sm.mt[W + t] = cm;
 #pragma unroll
     for (int j = 0; j < K; ++j) sm.tkind[t * K + j] = (uint8_t)ks[j];
     if (BOXES) {
@@ -373,39 +423,21 @@ __global__ __launch_bounds__(W) void k_resolve(
             }
         }
     }
-    __syncthreads();
-    mintree_build(sm.mt);
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        const int x = t + q * W;
+        if (x > aP) continue;
+        sm.inc_idx[x] = g_idx[q];
+        if (BOXES) sm.inc_ctx[x] = g_ctx[q];
+    }
+    mintree_build(sm.mt, cm);  // its barriers also publish everything above
 
-    // stack entry at absolute level L as seen from this thread's start
-    auto entry_at = [&](int64_t L) -> Ent {
-        Ent e{-1, box_inf(), -1, -1, -1, -1};
-        if (L <= 0) return e;
-        const int s = mintree_prev_less(sm.mt, t, L);
-        if (s >= 0) {
-            const int64_t jj = L - sm.tbase[s] - 1;
-            const uint32_t um = sm.tum[s];
-            if (jj < 0 || jj >= __popc(um)) return e;
-            const int p = nth_bit(um, (int)jj);
-            e.idx = p0 + (int64_t)s * K + p;
-            if (BOXES) e.ctx = isect(sm.jval[s], sm.ucum[s * K + p]);
-            e.kind = sm.tkind[s * K + p];
-            e.own = s;
-            e.pos = p;
-            return e;
-        }
-        const int64_t x = L - preM;
-        if (x < 0 || x > aP) return e;
-        const int slot = sm.inc_slot[x];
-        if (slot < 0) return e;
-        const uint32_t u = (uint32_t)U_idx[slot];
-        e.idx = (int64_t)(u & ~BLEND_BIT);
-        if (BOXES) e.ctx = sm.inc_ctx[x];
-        e.kind = (u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
-        e.slot = slot;
-        return e;
-    };
+    // levels at or below `lowtop` are held by no earlier thread of this
+    // partition: they come from earlier partitions (the LDS table).
+    const int64_t lowtop = min((int64_t)mintree_range_min(sm.mt, 0, t - 1), Dt);
 
-    // ---- clip context at each thread's base level: pointer jumping over threads
+    // ---- clip context at each thread's base level: pointer jumping along
+    // owner threads, first inside the wave with shuffles, then across waves.
     if (BOXES) {
         Box v = box_inf();
         int ptr = -1;
@@ -423,49 +455,66 @@ __global__ __launch_bounds__(W) void k_resolve(
                 if (x >= 0 && x <= aP) v = sm.inc_ctx[x];
             }
         }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const bool in = ptr >= wbase;
+            const int src = in ? ptr - wbase : lane;
+            const Box vv = {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE),
+                            __shfl(v.y1, src, WAVE)};
+            const int pp = __shfl(ptr, src, WAVE);
+            if (in) {
+                v = isect(v, vv);
+                ptr = pp;
+            }
+        }
         sm.jval[t] = v;
         sm.jptr[t] = ptr;
-        __syncthreads();
-        for (int r = 0; r < 8; ++r) {  // W = 2^8: every chain is resolved
-            Box vv = sm.jval[t];
-            int pp = sm.jptr[t];
-            if (pp >= 0) {
-                vv = isect(vv, sm.jval[pp]);
-                pp = sm.jptr[pp];
+        for (int r = 0; r < NWAVE && __syncthreads_or(ptr >= 0); ++r) {
+            if (ptr >= 0) {
+                v = isect(v, sm.jval[ptr]);
+                ptr = sm.jptr[ptr];
             }
             __syncthreads();
-            sm.jval[t] = vv;
-            sm.jptr[t] = pp;
-            __syncthreads();
+            sm.jval[t] = v;
+            sm.jptr[t] = ptr;
         }
+        __syncthreads();
     }
 
-    // ---- sequential walk over this thread's elements
+    // ---- sequential walk over this thread's elements with a register stack
+    // of local opens (index 0 = top; pushes and pops shift), each entry with
+    // its clip context and the union of leaves seen since it was opened.
     int64_t sid = off ? scene_of(off, S, g0) : 0;
     int64_t soff = off ? off[sid] : 0;
-    uint32_t mask = 0;
+    uint32_t defmask = 0;
+    int depth = 0;  // local stack depth
     bool rseen = false;
     int64_t dep = Dt;
-    Box cctx[K], lout[K];
-    int ndef = 0;
-    int def_j[K], def_own[K], def_pos[K], def_slot[K];
+    int st_pos[K], st_kind[K];
+    Box st_ctx[K], st_acc[K], lout[K];
+    int def_own[K], def_pos[K];
     int64_t def_L[K];
-    int64_t cur_L = INT64_MIN;
-    Ent cur{-1, box_inf(), -1, -1, -1, -1};
+    // the stack entry at level `cur_L` seen from this thread's start
+    int64_t cur_L = INT64_MIN, cur_idx = -1;
+    int cur_kind = -1, cur_own = -1, cur_pos = -1;
+    Box cur_ctx = box_inf();
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        cctx[j] = box_inf();
+        st_pos[j] = 0;
+        st_kind[j] = 0;
+        st_ctx[j] = box_inf();
+        st_acc[j] = box_empty();
         lout[j] = box_empty();
-        def_j[j] = def_own[j] = def_pos[j] = def_slot[j] = -1;
+        def_own[j] = def_pos[j] = -1;
         def_L[j] = 0;
     }
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int j = 0; j < K; ++j) {
         const int64_t i = g0 + j;
         const bool real = i < n;
         if ((rm >> j) & 1u) {
             if (real && i > 0 && dep != 0) flag(status, off, S, i - 1, ST_UNBAL);
-            mask = 0;
+            depth = 0;
             rseen = true;
             dep = 0;
             if (off && real) {
@@ -474,22 +523,49 @@ __global__ __launch_bounds__(W) void k_resolve(
             }
         }
         if (real && kr[j] > 4u) flag(status, off, S, i, ST_BAD_KIND);
+        if (depth == 0 && !rseen && cur_L != dep) {
+            cur_L = dep;
+            cur_idx = -1;
+            cur_kind = -1;
+            cur_own = -1;
+            cur_ctx = box_inf();
+            if (dep >= 1 && dep <= lowtop) {
+                const int64_t x = dep - preM;
+                if (x >= 0 && x <= aP) {
+                    const int u = sm.inc_idx[x];
+                    if (u != -1) {
+                        cur_idx = (int64_t)((uint32_t)u & ~BLEND_BIT);
+                        cur_kind = ((uint32_t)u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
+                        if (BOXES) cur_ctx = sm.inc_ctx[x];
+                    }
+                }
+            } else if (dep > lowtop) {
+                const int s = mintree_prev_less(sm.mt, t, dep);
+                if (s >= 0) {
+                    const int64_t jj = dep - sm.tbase[s] - 1;
+                    const uint32_t um = sm.tum[s];
+                    if (jj >= 0 && jj < __popc(um)) {
+                        const int p = nth_bit(um, (int)jj);
+                        cur_idx = p0 + (int64_t)s * K + p;
+                        if (BOXES) cur_ctx = isect(sm.jval[s], sm.ucum[s * K + p]);
+                        cur_kind = sm.tkind[s * K + p];
+                        cur_own = s;
+                        cur_pos = p;
+                    }
+                }
+            }
+        }
         int64_t top;
         Box ctx;
-        if (mask) {
-            const int p = msb32(mask);
-            top = g0 + p;
-            ctx = pick(cctx, p);
+        if (depth > 0) {
+            top = g0 + st_pos[0];
+            ctx = st_ctx[0];
         } else if (rseen) {
             top = -1;
             ctx = box_inf();
         } else {
-            if (cur_L != dep) {
-                cur = entry_at(dep);
-                cur_L = dep;
-            }
-            top = cur.idx;
-            ctx = cur.ctx;
+            top = cur_idx;
+            ctx = cur_ctx;
         }
         if (pm && real) pm[i] = top >= 0 ? (int32_t)(top - soff) : -1;
         const uint32_t k = ks[j];
@@ -497,99 +573,106 @@ __global__ __launch_bounds__(W) void k_resolve(
             if (BOXES) {
                 const Box o = canon(isect(bx[j], ctx));
                 lout[j] = o;
+                st_acc[0] = unite(st_acc[0], o);  // harmless when the stack is empty
                 if (real) st_box(out, i, o);
             }
             if (match && real) match[i] = -1;
-        } else if (k == BCLIP) {
-            if (BOXES) {
-                const Box c = isect(bx[j], ctx);
-                cctx[j] = c;
-                if (real) st_box(out, i, canon(c));
+        } else if (is_open(k)) {
+            Box c = ctx;
+            if (k == BCLIP) {
+                c = isect(bx[j], ctx);
+                if (BOXES && real) st_box(out, i, canon(c));
             }
-            mask |= 1u << j;
+#pragma unroll
+            for (int q = K - 1; q > 0; --q) {
+                st_pos[q] = st_pos[q - 1];
+                st_kind[q] = st_kind[q - 1];
+                st_ctx[q] = st_ctx[q - 1];
+                st_acc[q] = st_acc[q - 1];
+            }
+            st_pos[0] = j;
+            st_kind[0] = (int)k;
+            st_ctx[0] = c;
+            st_acc[0] = box_empty();
+            ++depth;
             ++dep;
-        } else if (k == BBLEND) {
-            cctx[j] = ctx;
-            mask |= 1u << j;
-            ++dep;
-        } else if (mask) {  // close matched inside this thread
-            const int p = msb32(mask);
-            mask &= ~(1u << p);
+        } else if (depth > 0) {  // close matched inside this thread
+            const int p = st_pos[0];
+            const int ko = st_kind[0];
+            const Box oc = st_ctx[0];
+            const Box acc = st_acc[0];
+#pragma unroll
+            for (int q = 0; q < K - 1; ++q) {
+                st_pos[q] = st_pos[q + 1];
+                st_kind[q] = st_kind[q + 1];
+                st_ctx[q] = st_ctx[q + 1];
+                st_acc[q] = st_acc[q + 1];
+            }
+            st_acc[0] = unite(st_acc[0], acc);  // leaves flow up to the new top
+            --depth;
             --dep;
-            const uint32_t ko = pick(ks, p);
-            if ((k == ECLIP) != (ko == BCLIP) && real) flag(status, off, S, i, ST_MISMATCH);
+            if ((k == ECLIP) != (ko == (int)BCLIP) && real) flag(status, off, S, i, ST_MISMATCH);
             if (match && real) {
                 match[i] = (int32_t)(g0 + p - soff);
                 match[g0 + p] = (int32_t)(i - soff);
             }
             if (BOXES && real) {
                 if (k == ECLIP) {
-                    st_box(out, i, canon(pick(cctx, p)));
+                    st_box(out, i, canon(oc));
                 } else {
-                    Box u = box_empty();
-#pragma unroll
-                    for (int q = 0; q < K; ++q)
-                        if (q > p && q < j) u = unite(u, lout[q]);
-                    st_box(out, i, u);
-                    st_box(out, g0 + p, u);
+                    st_box(out, i, acc);
+                    st_box(out, g0 + p, acc);
                 }
             }
         } else if (rseen) {  // close below its scene's root
             if (real) flag(status, off, S, i, ST_UNBAL);
-        } else {  // close of an open before this thread
+        } else {  // close of the open at level `dep`, held before this thread
             const int64_t L = dep;
-            Ent e{-1, box_inf(), -1, -1, -1, -1};
-            if (L <= 0) {
+            if (L <= 0 || cur_idx < 0) {
                 if (real) flag(status, off, S, i, ST_UNBAL);
             } else {
-                e = (cur_L == L) ? cur : entry_at(L);
-                if (e.idx < 0 && real) flag(status, off, S, i, ST_UNBAL);
-                if (e.kind >= 0 && ((k == ECLIP) != (e.kind == (int)BCLIP)) && real)
+                if (((k == ECLIP) != (cur_kind == (int)BCLIP)) && real)
                     flag(status, off, S, i, ST_MISMATCH);
                 if (match && real) {
-                    match[i] = e.idx >= 0 ? (int32_t)(e.idx - soff) : -1;
-                    if (e.idx >= 0 && e.idx < n) match[e.idx] = (int32_t)(i - soff);
+                    match[i] = (int32_t)(cur_idx - soff);
+                    if (cur_idx < n) match[cur_idx] = (int32_t)(i - soff);
                 }
                 if (BOXES && real) {
                     if (k == ECLIP) {
-                        st_box(out, i, canon(e.ctx));
+                        st_box(out, i, canon(cur_ctx));
                     } else {
-                        def_j[ndef] = j;
-                        def_L[ndef] = L;
-                        def_own[ndef] = e.own;
-                        def_pos[ndef] = e.pos;
-                        def_slot[ndef] = e.slot;
-                        ++ndef;
+                        defmask |= 1u << j;
+                        def_L[j] = L;
+                        def_own[j] = cur_own;
+                        def_pos[j] = cur_pos;
                     }
                 }
             }
             // every pop of a partition-incoming level leaves a record
-            if (BOXES && e.own < 0) {
+            if (BOXES && cur_own < 0) {
                 const int64_t ci = dP - L;
                 if (ci >= 0 && ci < aP) {
-                    const bool blend = (k == EBLEND) && e.slot >= 0 && real;
-                    cr_slot[p0 + ci] = blend ? e.slot : -1;
+                    int32_t sl = -1;
+                    if (k == EBLEND && real && L >= 1 && cur_idx >= 0) {
+                        int64_t R;
+                        sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, &R);
+                    }
+                    cr_slot[p0 + ci] = sl;
                     cr_c[p0 + ci] = (int32_t)i;
                 }
             }
             --dep;
         }
     }
-
     if (!BOXES) return;
 
     // ---- unions that cross threads or partitions
     Box ttot = box_empty();
 #pragma unroll
     for (int j = 0; j < K; ++j) ttot = unite(ttot, lout[j]);
-    sm.ut[W + t] = ttot;
-    __syncthreads();  // all reads of ucum / jval by entry_at are done
-    for (int w = W / 2; w >= 1; w >>= 1) {
-        if (t < w) sm.ut[w + t] = unite(sm.ut[2 * (w + t)], sm.ut[2 * (w + t) + 1]);
-        __syncthreads();
-    }
-    // suffix unions after each of this thread's unmatched opens
-    {
+    __syncthreads();  // the walk's reads of inc_ctx / jval / ucum are done
+    uniontree_build(ut, ttot);
+    {  // suffix unions after each of this thread's unmatched opens
         Box suf = box_empty();
 #pragma unroll
         for (int p = K - 1; p >= 0; --p) {
@@ -598,27 +681,28 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
     }
     __syncthreads();
-    for (int d = 0; d < ndef; ++d) {
-        const int j = def_j[d];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!((defmask >> j) & 1u)) continue;
         Box pre = box_empty();
 #pragma unroll
         for (int q = 0; q < K; ++q)
             if (q < j) pre = unite(pre, lout[q]);
         const int64_t i = g0 + j;
-        if (def_own[d] >= 0) {
-            const int s = def_own[d];
-            const Box u = unite(unite(sm.ucum[s * K + def_pos[d]], uniontree_range(sm.ut, s + 1, t - 1)), pre);
+        if (def_own[j] >= 0) {
+            const int s = def_own[j];
+            const Box u = unite(unite(sm.ucum[s * K + def_pos[j]], uniontree_range(ut, s + 1, t - 1)), pre);
             st_box(out, i, u);
-            st_box(out, p0 + (int64_t)s * K + def_pos[d], u);
+            st_box(out, p0 + (int64_t)s * K + def_pos[j], u);
         } else {
-            const int64_t ci = dP - def_L[d];
-            if (ci >= 0 && ci < aP) st_box(cr_pre, p0 + ci, unite(uniontree_range(sm.ut, 0, t - 1), pre));
+            const int64_t ci = dP - def_L[j];
+            if (ci >= 0 && ci < aP) st_box(cr_pre, p0 + ci, unite(uniontree_range(ut, 0, t - 1), pre));
         }
     }
     // surviving blend opens: union from the open to the end of the partition
     {
         const int sufmin = mintree_range_min(sm.mt, t + 1, W - 1);
-        const int64_t baseP = (int64_t)part[P].z;
+        const int64_t baseP = (int64_t)myp.z;
         int jj = 0;
 #pragma unroll
         for (int p = 0; p < K; ++p) {
@@ -628,10 +712,10 @@ __global__ __launch_bounds__(W) void k_resolve(
             if (L > (int64_t)sufmin || ks[p] != BBLEND) continue;
             const int64_t slot = L - baseP - 1;
             if (slot < 0 || slot >= T) continue;
-            st_box(U_suf, p0 + slot, unite(sm.ucum[t * K + p], uniontree_range(sm.ut, t + 1, W - 1)));
+            st_box(U_suf, p0 + slot, unite(sm.ucum[t * K + p], uniontree_range(ut, t + 1, W - 1)));
         }
     }
-    if (t == 0) st_box(ptot, P, sm.ut[1]);
+    if (t == 0) st_box(ptot, P, ut[1]);
 }
 
 // ------------------------------------------------ range unions over partitions
@@ -751,6 +835,8 @@ FwdLayout fwd_layout(int64_t n, int64_t S) {
     L.cr_slot = take(sizeof(int32_t) * M * T);
     L.cr_c = take(sizeof(int32_t) * M * T);
     L.cr_pre = take(sizeof(float4) * M * T);
+    L.runs = take(sizeof(int4) * M * RMAX);
+    L.rhead = take(sizeof(int4) * M);
     L.ptot = take(sizeof(float4) * M);
     L.upre = take(sizeof(float4) * M);
     L.usuf = take(sizeof(float4) * M);
@@ -802,17 +888,20 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
     int32_t *cr_c = (int32_t *)(w + L.cr_c);
     float4 *cr_pre = (float4 *)(w + L.cr_pre);
     float4 *ptot = (float4 *)(w + L.ptot);
+    int4 *runs = (int4 *)(w + L.runs);
+    int4 *rhead = (int4 *)(w + L.rhead);
+    k_runs<<<gM, 256, 0, st>>>(pinfo, part, M, runs, rhead);
     const bool prof = g_prof_before && g_prof_after;
-    if (prof) hipEventRecord(g_prof_before, st);
+    if (prof) (void)hipEventRecord(g_prof_before, st);
     if (boxes)
-        k_resolve<true><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, jv[cur], U_idx,
+        k_resolve<true><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx,
                                                     U_cum, U_suf, cr_slot, cr_c, cr_pre, ptot, match,
                                                     pm, out, status);
     else
-        k_resolve<false><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, jv[cur],
+        k_resolve<false><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur],
                                                      U_idx, U_cum, U_suf, cr_slot, cr_c, cr_pre,
                                                      ptot, match, pm, out, status);
-    if (prof) hipEventRecord(g_prof_after, st);
+    if (prof) (void)hipEventRecord(g_prof_after, st);
     if (boxes) {
         float4 *upre = (float4 *)(w + L.upre);
         float4 *usuf = (float4 *)(w + L.usuf);
