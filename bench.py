@@ -63,12 +63,77 @@ def cpu_baseline(budget_s=12.0):
                       f"median of {len(times)} runs, {best:.3f} s each"}
 
 
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def batched_section(steps, warmup):
+    """2048 ragged scenes: one tb_bbox_batched launch vs one graph-captured
+    tb_bbox call per scene (same rows, byte-compared)."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    c = gen.config(3)
+    n = len(c["kind"])
+    kind, box = torch.from_numpy(c["kind"].view(np.int32)).cuda(), torch.from_numpy(c["box"]).cuda()
+    off = torch.from_numpy(c["offsets"]).cuda()
+    out = {}
+    ms_b = time_steps(lambda: tb.tb_bbox_batched(kind, box, off), steps, warmup)
+    bout, bm, bst = tb.tb_bbox_batched(kind, box, off)
+    g = tb.PerSceneGraph(kind, box, c["offsets"])
+    ms_g = time_steps(g.replay, steps, warmup)
+    gout, gm, gst = g.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(bout.view(torch.int32), gout.view(torch.int32)) and torch.equal(bm, gm)
+                and int(bst.abs().sum()) == 0 and int(gst.abs().sum()) == 0)
+    out.update({"workload": "batch-2048-ragged", "elements": n, "scenes": len(c["offsets"]) - 1,
+                "batched_ms": round(ms_b, 4), "batched_gelem_s": round(n / ms_b / 1e6, 3),
+                "per_scene_graph_ms": round(ms_g, 4), "per_scene_graph_gelem_s": round(n / ms_g / 1e6, 3),
+                "speedup": round(ms_g / ms_b, 3), "byte_identical": same})
+    return out
+
+
+def fwd_bwd_section(steps, warmup):
+    """Forward + backward on the 2^24-element gradient workload."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    c = gen.config(4)
+    n = len(c["kind"])
+    kind = torch.from_numpy(c["kind"].view(np.int32)).cuda()
+    box = torch.from_numpy(c["box"]).cuda()
+    g = torch.from_numpy(c["grad"]).cuda()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    m = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def step():
+        tb.tb_bbox(kind, box, match=m, out=out, status=st)
+        tb.tb_bbox_backward(kind, box, g)
+
+    ms = time_steps(step, steps, warmup)
+    return {"workload": "scene-16M-cap256-grad", "elements": n, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(92 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -131,6 +196,11 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "kernel_ms": round(k_ms, 4), "traffic": None},
     }
+    if not args.no_extra:
+        del kind, box, out, match
+        torch.cuda.empty_cache()
+        res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2)
+        res["fwd_bwd"] = fwd_bwd_section(max(3, args.steps // 2), 2)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

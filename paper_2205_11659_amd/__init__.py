@@ -185,3 +185,44 @@ class TreeBBoxFn(torch.autograd.Function):
 def bbox(kind, box):
     out, _, _ = TreeBBoxFn.apply(kind, box)
     return out
+
+
+class PerSceneGraph:
+    """One tb_bbox call per scene, captured once into a HIP graph (the
+    baseline that tb_bbox_batched is compared with).  Outputs are views of
+    one (n, 4) box buffer and one int32 match buffer, so the rows line up
+    with the batched call's; status holds one word per scene."""
+
+    def __init__(self, kind, box, offsets_host):
+        n = kind.numel()
+        dev = kind.device
+        self.kind, self.box = _as_kind(kind), _as_box(box, n)
+        self.out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        self.match = torch.empty(n, dtype=torch.int32, device=dev)
+        S = len(offsets_host) - 1
+        self.status = torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+        offs = [int(v) for v in offsets_host]
+        big = max([b - a for a, b in zip(offs[:-1], offs[1:])] + [0])
+        need = lib().tb_workspace_bytes(OP_BBOX, big, 1)
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        wsp = self.ws.data_ptr() + ((-self.ws.data_ptr()) % 256)
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(self.graph, stream=side):
+                st = _stream()
+                for s in range(S):
+                    a, b = offs[s], offs[s + 1]
+                    _check(lib().tb_bbox(
+                        ctypes.c_void_p(self.kind.data_ptr() + 4 * a),
+                        ctypes.c_void_p(self.box.data_ptr() + 16 * a), b - a,
+                        ctypes.c_void_p(self.match.data_ptr() + 4 * a),
+                        ctypes.c_void_p(self.out.data_ptr() + 16 * a),
+                        ctypes.c_void_p(wsp), need,
+                        ctypes.c_void_p(self.status.data_ptr() + 4 * s), st))
+        torch.cuda.current_stream().wait_stream(side)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out, self.match, self.status

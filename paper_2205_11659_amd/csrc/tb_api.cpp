@@ -8,7 +8,7 @@
 
 namespace {
 
-constexpr int64_t MAX_N = (int64_t)1 << 31;
+constexpr int64_t MAX_N = (int64_t)1 << 31;  // indices are int32
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -17,12 +17,12 @@ size_t ws_bytes_for(int op, int64_t n, int64_t S) {
     switch (op) {
     case TB_OP_MATCH:
     case TB_OP_BBOX:
-        return tb::fwd_layout(n, 1).total;
+        return tb::fwd_layout(n, 1, 16, false).total;
     case TB_OP_BBOX_BATCHED:
         if (S < 1 || S >= MAX_N) return 0;
-        return tb::fwd_layout(n, S).total;
+        return tb::fwd_layout(n, S, 16, false).total;
     case TB_OP_BBOX_BACKWARD:
-        return 0;  // not available in this build
+        return tb::fwd_layout(n, 1, 32, true).total;
     default:
         return 0;
     }
@@ -94,9 +94,15 @@ tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int6
 tb_status tb_bbox_backward(const uint32_t *kind, const tb_box *box_in, const tb_box *grad_out,
                            int64_t n, tb_box *grad_in, void *ws, size_t ws_bytes,
                            uint32_t *dev_status, void *stream) {
-    (void)kind, (void)box_in, (void)grad_out, (void)n, (void)grad_in, (void)ws, (void)ws_bytes,
-        (void)dev_status, (void)stream;
-    return TB_ERR_ARG;
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!dev_status || (n > 0 && (!box_in || !grad_out || !grad_in))) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (box_in && !aligned(box_in, 16)) ||
+        (grad_out && !aligned(grad_out, 16)) || (grad_in && !aligned(grad_in, 16)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(kind, n, ws, ws_bytes, TB_OP_BBOX_BACKWARD, 1);
+    if (c != TB_OK) return c;
+    return launched(tb::bwd_run(kind, (const float4 *)box_in, (const float4 *)grad_out, n,
+                                (float4 *)grad_in, ws, dev_status, (hipStream_t)stream));
 }
 
 void tb_profile_events(void *before, void *after) {

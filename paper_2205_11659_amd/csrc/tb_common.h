@@ -49,16 +49,104 @@ __device__ __forceinline__ void st_box(float4 *p, int64_t i, Box b) {
     p[i] = make_float4(b.x0, b.y0, b.x1, b.y1);
 }
 
+// Box with, per coordinate, the index of the input element attaining it
+// (the gradient's route).  max/min keep the attaining index; on equal values
+// the lower index wins, so the combine stays associative, commutative and
+// idempotent and every combine order yields the same (value, index) pair.
+struct BoxS {
+    float x0, y0, x1, y1;
+    int32_t s0, s1, s2, s3;
+};
+constexpr int32_t NOSRC = INT32_MAX;  // identity elements route nowhere
+
+__device__ __forceinline__ void mx(float &v, int32_t &s, float w, int32_t t) {
+    if (w > v || (w == v && t < s)) v = w, s = t;
+}
+__device__ __forceinline__ void mn(float &v, int32_t &s, float w, int32_t t) {
+    if (w < v || (w == v && t < s)) v = w, s = t;
+}
+__device__ __forceinline__ BoxS isect(BoxS a, const BoxS &b) {
+    mx(a.x0, a.s0, b.x0, b.s0), mx(a.y0, a.s1, b.y0, b.s1);
+    mn(a.x1, a.s2, b.x1, b.s2), mn(a.y1, a.s3, b.y1, b.s3);
+    return a;
+}
+__device__ __forceinline__ BoxS unite(BoxS a, const BoxS &b) {
+    mn(a.x0, a.s0, b.x0, b.s0), mn(a.y0, a.s1, b.y0, b.s1);
+    mx(a.x1, a.s2, b.x1, b.s2), mx(a.y1, a.s3, b.y1, b.s3);
+    return a;
+}
+__device__ __forceinline__ BoxS canon(BoxS a) {
+    if (a.x0 < a.x1 && a.y0 < a.y1) return a;
+    return {INFINITY, INFINITY, -INFINITY, -INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
+}
+
+// Payload traits: identities, own element, workspace load/store.
+template <class V>
+struct Pay;
+template <>
+struct Pay<Box> {
+    static __device__ __forceinline__ Box inf() { return box_inf(); }
+    static __device__ __forceinline__ Box empty() { return box_empty(); }
+    static __device__ __forceinline__ Box own(float4 b, int64_t) { return {b.x, b.y, b.z, b.w}; }
+    static __device__ __forceinline__ Box ld(const void *base, int64_t i) {
+        return ld_box((const float4 *)base, i);
+    }
+    static __device__ __forceinline__ void st(void *base, int64_t i, Box v) {
+        st_box((float4 *)base, i, v);
+    }
+    static __device__ __forceinline__ bool nonempty(const Box &v) { return v.x0 < v.x1 && v.y0 < v.y1; }
+};
+template <>
+struct Pay<BoxS> {
+    static __device__ __forceinline__ BoxS inf() {
+        return {-INFINITY, -INFINITY, INFINITY, INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
+    }
+    static __device__ __forceinline__ BoxS empty() {
+        return {INFINITY, INFINITY, -INFINITY, -INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
+    }
+    static __device__ __forceinline__ BoxS own(float4 b, int64_t i) {
+        const int32_t s = (int32_t)i;
+        return {b.x, b.y, b.z, b.w, s, s, s, s};
+    }
+    static __device__ __forceinline__ BoxS ld(const void *base, int64_t i) {
+        const float4 v = ((const float4 *)base)[2 * i];
+        const int4 s = ((const int4 *)base)[2 * i + 1];
+        return {v.x, v.y, v.z, v.w, s.x, s.y, s.z, s.w};
+    }
+    static __device__ __forceinline__ void st(void *base, int64_t i, const BoxS &v) {
+        ((float4 *)base)[2 * i] = make_float4(v.x0, v.y0, v.x1, v.y1);
+        ((int4 *)base)[2 * i + 1] = make_int4(v.s0, v.s1, v.s2, v.s3);
+    }
+    static __device__ __forceinline__ bool nonempty(const BoxS &v) { return v.x0 < v.x1 && v.y0 < v.y1; }
+};
+
 // ---------------------------------------------------------- wave shuffles
 __device__ __forceinline__ int shfl_up(int v, int d) { return __shfl_up(v, d, WAVE); }
 __device__ __forceinline__ float shfl_up(float v, int d) { return __shfl_up(v, d, WAVE); }
 __device__ __forceinline__ Box shfl_up(Box v, int d) {
     return {shfl_up(v.x0, d), shfl_up(v.y0, d), shfl_up(v.x1, d), shfl_up(v.y1, d)};
 }
+__device__ __forceinline__ BoxS shfl_up(BoxS v, int d) {
+    return {shfl_up(v.x0, d), shfl_up(v.y0, d), shfl_up(v.x1, d), shfl_up(v.y1, d),
+            shfl_up((int)v.s0, d), shfl_up((int)v.s1, d), shfl_up((int)v.s2, d), shfl_up((int)v.s3, d)};
+}
 __device__ __forceinline__ int shfl_xor(int v, int m) { return __shfl_xor(v, m, WAVE); }
 __device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, WAVE); }
 __device__ __forceinline__ Box shfl_xor(Box v, int m) {
     return {shfl_xor(v.x0, m), shfl_xor(v.y0, m), shfl_xor(v.x1, m), shfl_xor(v.y1, m)};
+}
+__device__ __forceinline__ BoxS shfl_xor(BoxS v, int m) {
+    return {shfl_xor(v.x0, m), shfl_xor(v.y0, m), shfl_xor(v.x1, m), shfl_xor(v.y1, m),
+            shfl_xor((int)v.s0, m), shfl_xor((int)v.s1, m), shfl_xor((int)v.s2, m), shfl_xor((int)v.s3, m)};
+}
+// arbitrary-lane reads
+__device__ __forceinline__ Box shfl_idx(Box v, int src) {
+    return {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE), __shfl(v.y1, src, WAVE)};
+}
+__device__ __forceinline__ BoxS shfl_idx(BoxS v, int src) {
+    return {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE), __shfl(v.y1, src, WAVE),
+            __shfl((int)v.s0, src, WAVE), __shfl((int)v.s1, src, WAVE), __shfl((int)v.s2, src, WAVE),
+            __shfl((int)v.s3, src, WAVE)};
 }
 
 // Segmented sum: (r, v) with r = "a reset occurs in this range"; a reset
@@ -77,10 +165,12 @@ struct AddOp {
     __device__ int operator()(int a, int b) const { return a + b; }
 };
 struct IsectOp {
-    __device__ Box operator()(Box a, Box b) const { return isect(a, b); }
+    template <class V>
+    __device__ V operator()(V a, V b) const { return isect(a, b); }
 };
 struct UniteOp {
-    __device__ Box operator()(Box a, Box b) const { return unite(a, b); }
+    template <class V>
+    __device__ V operator()(V a, V b) const { return unite(a, b); }
 };
 
 template <class V, class Op>
@@ -249,7 +339,8 @@ __device__ __forceinline__ void mintree_build(int *mt, int v) {
 }
 
 // The same for a union tree of boxes.
-__device__ __forceinline__ void uniontree_build(Box *ut, Box v) {
+template <class V>
+__device__ __forceinline__ void uniontree_build(V *ut, V v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
     ut[W + t] = v;
 #pragma unroll
@@ -291,8 +382,9 @@ __device__ __forceinline__ int mintree_range_min(const int *mt, int lo, int hi) 
 }
 
 // union over leaves [lo, hi] of an LDS segment tree of boxes (EMPTY if empty)
-__device__ __forceinline__ Box uniontree_range(const Box *ut, int lo, int hi) {
-    Box r = box_empty();
+template <class V>
+__device__ __forceinline__ V uniontree_range(const V *ut, int lo, int hi) {
+    V r = Pay<V>::empty();
     if (lo > hi) return r;
     int l = lo + W, h = hi + W + 1;
     while (l < h) {

@@ -11,19 +11,25 @@ namespace tb {
 struct FwdLayout {
     int64_t M, Mp, nb;
     int levels;
-    size_t pinfo, part, mtree, jptr0, jptr1, jval0, jval1;
+    size_t pinfo, part, mtree, bagg, jptr0, jptr1, jval0, jval1;
     size_t U_idx, U_cum, U_suf, cr_slot, cr_c, cr_pre;
-    size_t runs, rhead, ptot, upre, usuf, sp, status;
+    size_t runs, rhead, ptot, upre, usuf, sp, status, acc, selfm;
     size_t total;
 };
 
-FwdLayout fwd_layout(int64_t n, int64_t S);
+// vbytes: payload size (16 forward, 32 backward); grad adds the gradient
+// accumulators.
+FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad);
 
 // Enqueue the forward pipeline.  boxes=false computes matching only.
 // off == nullptr means one scene.  status may be nullptr (workspace word).
 hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t n,
                    const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
                    void *ws, uint32_t *status, hipStream_t st);
+
+// Enqueue the gradient pass (recompute with attaining indices + exact sums).
+hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,
+                   float4 *grad_in, void *ws, uint32_t *status, hipStream_t st);
 
 // Events recorded around the main per-partition kernel (nullptr = off).
 extern hipEvent_t g_prof_before, g_prof_after;

@@ -51,16 +51,15 @@ __global__ void k_check_offsets(const int64_t *off, int64_t S, int64_t n, uint32
 }
 
 // ---------------------------------------------------------------- k_reduce
-template <bool BOXES>
+template <bool BOXES, class V>
 __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
                                               const float4 *__restrict__ box, int64_t n,
                                               const int64_t *__restrict__ off, int64_t S,
                                               int4 *__restrict__ pinfo,
-                                              int32_t *__restrict__ U_idx,
-                                              float4 *__restrict__ U_cum) {
+                                              int32_t *__restrict__ U_idx, void *__restrict__ U_cum) {
     __shared__ Seg sh_seg[NWAVE];
     __shared__ int sh_i[NWAVE];
-    __shared__ Box sh_b[NWAVE];
+    __shared__ V sh_b[NWAVE];
     __shared__ int mt[2 * W];
     const int t = threadIdx.x;
     const int64_t P = blockIdx.x;
@@ -97,16 +96,16 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
     int ns = 0;
     if ((int64_t)sufmin > (int64_t)base) ns = (int)min((int64_t)b, (int64_t)sufmin - base);
 
-    Box agg = box_inf(), bxs[K];
+    V agg = Pay<V>::inf(), bxs[K];
     uint32_t clipmask = 0;
     if (BOXES) {
         int jj = 0;
 #pragma unroll
         for (int p = 0; p < K; ++p) {
-            bxs[p] = box_inf();
+            bxs[p] = Pay<V>::inf();
             if ((wk.umask >> p) & 1u) {
                 if (jj < ns && ks[p] == BCLIP) {
-                    bxs[p] = ld_box(box, g0 + p);
+                    bxs[p] = Pay<V>::own(box[g0 + p], g0 + p);
                     agg = isect(agg, bxs[p]);
                     clipmask |= 1u << p;
                 }
@@ -114,8 +113,8 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
             }
         }
     }
-    Box aggtot;
-    Box cum = BOXES ? block_excl_scan<NWAVE>(agg, IsectOp{}, box_inf(), sh_b, &aggtot) : box_inf();
+    V aggtot;
+    V cum = BOXES ? block_excl_scan<NWAVE>(agg, IsectOp{}, Pay<V>::inf(), sh_b, &aggtot) : Pay<V>::inf();
     int nsum;
     block_excl_scan<NWAVE>(ns, AddOp{}, 0, sh_i, &nsum);
 
@@ -130,7 +129,7 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
                 U_idx[P * T + slot] = (int32_t)((uint32_t)(g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
                 if (BOXES) {
                     if ((clipmask >> p) & 1u) cum = isect(cum, bxs[p]);
-                    st_box(U_cum, P * T + slot, cum);
+                    Pay<V>::st(U_cum, P * T + slot, cum);
                 }
             }
         }
@@ -140,44 +139,98 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
 }
 
 // ------------------------------------------------------------ spine kernels
-// One workgroup of SPW threads: segmented exclusive depth scan over the M
-// partition summaries, partition records {d, cm, base, link}, the min tree
-// over cm, and the end-of-sequence balance check.
-constexpr int SPW = 1024;
+// Segmented exclusive depth scan over the M partition summaries, in blocks
+// of SB partitions (reduce, scan of block totals, apply), then partition
+// records {d, cm, base, link} and a min tree over cm (each block builds its
+// own subtree in LDS; one workgroup finishes the top).
+constexpr int SB = 1024;
 
-__global__ __launch_bounds__(SPW) void k_spine_scan(const int4 *__restrict__ pinfo, int64_t M,
-                                                     int4 *__restrict__ part, int *__restrict__ mtree,
-                                                     int64_t Mp, const int64_t *__restrict__ off,
-                                                     int64_t S, int64_t n,
-                                                     uint32_t *__restrict__ status) {
-    __shared__ Seg sh_seg[SPW / WAVE];
+__device__ __forceinline__ Seg part_seg(int4 v) { return Seg{v.z, v.z ? v.y : v.y - v.x}; }
+
+__global__ __launch_bounds__(SB) void k_spine_blocks(const int4 *__restrict__ pinfo, int64_t M,
+                                                     int2 *__restrict__ bagg) {
+    __shared__ Seg sh[SB / WAVE];
+    const int64_t P = (int64_t)blockIdx.x * SB + threadIdx.x;
+    const Seg v = P < M ? part_seg(pinfo[P]) : Seg{0, 0};
+    Seg tot;
+    block_excl_scan<SB / WAVE>(v, SegOp{}, Seg{0, 0}, sh, &tot);
+    if (threadIdx.x == 0) bagg[blockIdx.x] = make_int2(tot.r, tot.v);
+}
+
+// exclusive scan of the block totals (nbk <= SB * SPT), in place; checks
+// that the whole sequence ends at depth 0
+constexpr int SPT = 4;
+__global__ __launch_bounds__(SB) void k_spine_top(int2 *__restrict__ bagg, int64_t nbk,
+                                                  const int64_t *__restrict__ off, int64_t S,
+                                                  int64_t n, uint32_t *__restrict__ status) {
+    __shared__ Seg sh[SB / WAVE];
     const int t = threadIdx.x;
-    const int64_t ipt = (M + SPW - 1) / SPW;
-    const int64_t lo = t * ipt, hi = min(M, lo + ipt);
-    Seg agg{0, 0};
-    for (int64_t P = lo; P < hi; ++P) {
-        int4 v = pinfo[P];
-        agg = SegOp{}(agg, Seg{v.z, v.z ? v.y : v.y - v.x});
+    Seg v[SPT], agg{0, 0};
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int64_t b = (int64_t)t * SPT + q;
+        const int2 x = b < nbk ? bagg[b] : make_int2(0, 0);
+        v[q] = Seg{x.x, x.y};
+        agg = SegOp{}(agg, v[q]);
     }
     Seg tot;
-    Seg ex = block_excl_scan<SPW / WAVE>(agg, SegOp{}, Seg{0, 0}, sh_seg, &tot);
-    int d = ex.v;
-    for (int64_t P = lo; P < hi; ++P) {
-        int4 v = pinfo[P];
-        const int pre_m = d - v.x;
-        const int cm = v.z ? SENT : pre_m;
-        part[P] = make_int4(d, cm, v.z ? 0 : pre_m, -1);
-        mtree[Mp + P] = cm;
-        d = v.z ? v.y : d - v.x + v.y;
+    Seg ex = block_excl_scan<SB / WAVE>(agg, SegOp{}, Seg{0, 0}, sh, &tot);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int64_t b = (int64_t)t * SPT + q;
+        if (b < nbk) bagg[b] = make_int2(ex.r, ex.v);
+        ex = SegOp{}(ex, v[q]);
     }
-    for (int64_t P = M + t; P < Mp; P += SPW) mtree[Mp + P] = INT32_MAX;
     if (t == 0 && tot.v != 0 && n > 0) flag(status, off, S, n - 1, ST_UNBAL);
+}
+
+// blocks cover [0, Mp): partition records, min-tree leaves and the block's
+// subtree (padding leaves hold INT32_MAX)
+__global__ __launch_bounds__(SB) void k_spine_apply(const int4 *__restrict__ pinfo, int64_t M,
+                                                    const int2 *__restrict__ bex,
+                                                    int4 *__restrict__ part, int *__restrict__ mtree,
+                                                    int64_t Mp) {
+    __shared__ Seg sh[SB / WAVE];
+    __shared__ int lt[SB];
+    const int t = threadIdx.x;
+    const int64_t B = blockIdx.x;
+    const int64_t P = B * SB + t;
+    const int4 pv = P < M ? pinfo[P] : make_int4(0, 0, 0, 0);
+    const Seg v = P < M ? part_seg(pv) : Seg{0, 0};
+    Seg tot;
+    const Seg loc = block_excl_scan<SB / WAVE>(v, SegOp{}, Seg{0, 0}, sh, &tot);
+    int cm = INT32_MAX;
+    if (P < M) {
+        const int2 bx = bex[B];
+        const Seg ex = SegOp{}(Seg{bx.x, bx.y}, loc);
+        const int d = ex.v;
+        const int pre_m = d - pv.x;
+        cm = pv.z ? SENT : pre_m;
+        part[P] = make_int4(d, cm, pv.z ? 0 : pre_m, -1);
+    }
+    if (P < Mp) mtree[Mp + P] = cm;
+    // subtree of this block: leaves lt[0..w), halving until one node
+    const int64_t span = Mp < SB ? Mp : SB;
+    lt[t] = cm;
     __syncthreads();
-    for (int64_t w = Mp / 2; w >= 1; w >>= 1) {
-        for (int64_t x = w + t; x < 2 * w; x += SPW) {
-            int a = mtree[2 * x], b = mtree[2 * x + 1];
-            mtree[x] = a < b ? a : b;
+    int64_t base = Mp + B * SB;  // node index of this block's first leaf
+    for (int64_t w = span / 2; w >= 1; w >>= 1) {
+        base >>= 1;
+        int m = INT32_MAX;
+        if (t < w) m = min(lt[2 * t], lt[2 * t + 1]);
+        __syncthreads();
+        if (t < w) {
+            lt[t] = m;
+            mtree[base + t] = m;
         }
+        __syncthreads();
+    }
+}
+
+// levels above the block subtrees: nodes [1, Mp / SB)
+__global__ __launch_bounds__(SB) void k_spine_treetop(int *__restrict__ mtree, int64_t Mp) {
+    for (int64_t w = Mp / SB / 2; w >= 1; w >>= 1) {
+        for (int64_t x = w + threadIdx.x; x < 2 * w; x += SB) mtree[x] = min(mtree[2 * x], mtree[2 * x + 1]);
         __syncthreads();
     }
 }
@@ -196,11 +249,11 @@ __device__ __forceinline__ int64_t gtree_prev_less(const int *mt, int64_t Mp, in
     return -1;
 }
 
-template <bool BOXES>
+template <bool BOXES, class V>
 __global__ void k_spine_link(const int4 *__restrict__ pinfo, int4 *__restrict__ part, int64_t M,
                              const int *__restrict__ mtree, int64_t Mp,
-                             const float4 *__restrict__ U_cum, int32_t *__restrict__ jptr,
-                             float4 *__restrict__ jval) {
+                             const void *__restrict__ U_cum, int32_t *__restrict__ jptr,
+                             void *__restrict__ jval) {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= M) return;
     int4 pr = part[P];
@@ -209,31 +262,32 @@ __global__ void k_spine_link(const int4 *__restrict__ pinfo, int4 *__restrict__ 
     if (cm != SENT) link = gtree_prev_less(mtree, Mp, P, cm);
     part[P].w = (int)link;
     if (!BOXES) return;
-    Box val = box_inf();
+    V val = Pay<V>::inf();
     int64_t ptr = -1;
     if (cm != SENT && cm > 0 && link >= 0) {
         const int64_t slot = cm - (int64_t)part[link].z - 1;
         if (slot >= 0 && slot < pinfo[link].y) {
-            val = ld_box(U_cum, link * T + slot);
+            val = Pay<V>::ld(U_cum, link * T + slot);
             ptr = link;
         }
     }
     jptr[P] = (int32_t)ptr;
-    st_box(jval, P, val);
+    Pay<V>::st(jval, P, val);
 }
 
-__global__ void k_jump(const int32_t *__restrict__ ptr_in, const float4 *__restrict__ val_in,
-                       int32_t *__restrict__ ptr_out, float4 *__restrict__ val_out, int64_t M) {
+template <class V>
+__global__ void k_jump(const int32_t *__restrict__ ptr_in, const void *__restrict__ val_in,
+                       int32_t *__restrict__ ptr_out, void *__restrict__ val_out, int64_t M) {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= M) return;
     int32_t p = ptr_in[P];
-    Box v = ld_box(val_in, P);
+    V v = Pay<V>::ld(val_in, P);
     if (p >= 0) {
-        v = isect(v, ld_box(val_in, p));
+        v = isect(v, Pay<V>::ld(val_in, p));
         p = ptr_in[p];
     }
     ptr_out[P] = p;
-    st_box(val_out, P, v);
+    Pay<V>::st(val_out, P, v);
 }
 
 // ---------------------------------------------------------------- k_runs
@@ -267,17 +321,6 @@ __global__ void k_runs(const int4 *__restrict__ pinfo, const int4 *__restrict__ 
 }
 
 // ------------------------------------------------------------- k_resolve
-// Stack entry at some level as seen from the start of a thread.
-struct Ent {
-    int64_t idx;  // element index of the open, -1 = root
-    Box ctx;      // clip context of the entry (its children's context)
-    int kind;     // kind of the open (BCLIP/BBLEND), -1 for root
-    int own;      // owning thread in this partition, or -1
-    int pos;      // position of the open in the owning thread
-    int slot;     // global U slot when owned by an earlier partition, else -1
-};
-
-__device__ __forceinline__ Ent ent_root() { return Ent{-1, box_inf(), -1, -1, -1, -1}; }
 
 // Owner run holding level L (runs cover disjoint level ranges, highest
 // first): binary search; -1 if L lies below the stored runs.
@@ -324,37 +367,38 @@ __device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 he
     return R * T + (L - base - 1);
 }
 
-template <bool BOXES>
+template <bool BOXES, class V>
 struct ResolveSmem {
     int4 runs[RMAX];
     // incoming levels [preM, dP], entry x = level preM + x: the open's index
     // (| BLEND_BIT) or -1 for the root, and its clip context.  After the walk
     // the context array is reused as the union tree over threads.
     int inc_idx[T + 1];
-    Box inc_ctx[BOXES ? T + 1 : 1];
-    Box ucum[BOXES ? T : 1];  // local clip prefix of thread U entries; later suffix unions
-    Box jval[BOXES ? W : 1];  // clip context at each thread's base level
+    V inc_ctx[BOXES ? T + 1 : 1];
+    V ucum[BOXES ? T : 1];  // local clip prefix of thread U entries; later suffix unions
+    V jval[BOXES ? W : 1];  // clip context at each thread's base level
     uint8_t tkind[T];
     int tcm[W];
     int tbase[W];
     uint8_t tum[W];
     int mt[2 * W];
+    int tlink[W];  // owner thread of each thread's base level (prev smaller cm), or -1
     int jptr[W];
     Seg sh_seg[NWAVE];
 };
 
-template <bool BOXES>
+template <bool BOXES, class V, class SINK>
 __global__ __launch_bounds__(W) void k_resolve(
     const uint32_t *__restrict__ kind, const float4 *__restrict__ box, int64_t n,
     const int64_t *__restrict__ off, int64_t S, const int4 *__restrict__ pinfo,
     const int4 *__restrict__ part, const int4 *__restrict__ runs_g,
-    const int4 *__restrict__ rhead_g, const float4 *__restrict__ base_ctx,
-    const int32_t *__restrict__ U_idx, const float4 *__restrict__ U_cum,
-    float4 *__restrict__ U_suf, int32_t *__restrict__ cr_slot, int32_t *__restrict__ cr_c,
-    float4 *__restrict__ cr_pre, float4 *__restrict__ ptot, int32_t *__restrict__ match,
-    int32_t *__restrict__ pm, float4 *__restrict__ out, uint32_t *__restrict__ status) {
-    __shared__ ResolveSmem<BOXES> sm;
-    Box *ut = sm.inc_ctx;  // valid once the walk is over
+    const int4 *__restrict__ rhead_g, const void *__restrict__ base_ctx,
+    const int32_t *__restrict__ U_idx, const void *__restrict__ U_cum,
+    void *__restrict__ U_suf, int32_t *__restrict__ cr_slot, int32_t *__restrict__ cr_c,
+    void *__restrict__ cr_pre, void *__restrict__ ptot, int32_t *__restrict__ match,
+    int32_t *__restrict__ pm, SINK sink, uint32_t *__restrict__ status) {
+    __shared__ ResolveSmem<BOXES, V> sm;
+    V *ut = sm.inc_ctx;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
     const int64_t P = blockIdx.x;
     const int64_t p0 = P * T;
@@ -369,10 +413,10 @@ __global__ __launch_bounds__(W) void k_resolve(
     // ---- loads: inputs, owner runs
     uint32_t kr[K], ks[K];
     load_kinds(kind, n, g0, kr);
-    Box bx[K];
+    V bx[K];
     if (BOXES) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) bx[j] = (g0 + j < n) ? ld_box(box, g0 + j) : box_empty();
+        for (int j = 0; j < K; ++j) bx[j] = (g0 + j < n) ? Pay<V>::own(box[g0 + j], g0 + j) : Pay<V>::empty();
     }
     if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
@@ -383,11 +427,11 @@ __global__ __launch_bounds__(W) void k_resolve(
     // ---- gather the incoming levels [preM, dP] (issued now, stored later)
     constexpr int NG = (T + W) / W;  // entries per thread
     int g_idx[NG];
-    Box g_ctx[NG];
+    V g_ctx[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
         g_idx[q] = -1;
-        g_ctx[q] = box_inf();
+        g_ctx[q] = Pay<V>::inf();
         const int x = t + q * W;
         const int64_t L = preM + x;
         if (x > aP || L < 1) continue;
@@ -395,7 +439,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         const int64_t slot = incoming_slot(L, sm.runs, nruns, head, part, &R);
         if (slot < 0) continue;
         g_idx[q] = U_idx[slot];
-        if (BOXES) g_ctx[q] = isect(ld_box(U_cum, slot), ld_box(base_ctx, R));
+        if (BOXES) g_ctx[q] = isect(Pay<V>::ld(U_cum, slot), Pay<V>::ld(base_ctx, R));
     }
 
     // ---- per-thread walk and thread-level depths
@@ -414,7 +458,7 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
     for (int j = 0; j < K; ++j) sm.tkind[t * K + j] = (uint8_t)ks[j];
     if (BOXES) {
-        Box c = box_inf();
+        V c = Pay<V>::inf();
 #pragma unroll
         for (int p = 0; p < K; ++p) {
             if ((wk.umask >> p) & 1u) {
@@ -435,14 +479,18 @@ __global__ __launch_bounds__(W) void k_resolve(
     // levels at or below `lowtop` are held by no earlier thread of this
     // partition: they come from earlier partitions (the LDS table).
     const int64_t lowtop = min((int64_t)mintree_range_min(sm.mt, 0, t - 1), Dt);
+    // owner links between threads: the entry just below a thread's lowest
+    // level belongs to the nearest earlier thread with a smaller lowest level
+    const int tl = wk.rs ? -1 : mintree_prev_less(sm.mt, t, cm);
+    sm.tlink[t] = tl;
 
     // ---- clip context at each thread's base level: pointer jumping along
     // owner threads, first inside the wave with shuffles, then across waves.
     if (BOXES) {
-        Box v = box_inf();
+        V v = Pay<V>::inf();
         int ptr = -1;
         if (!wk.rs && pre_m > 0) {
-            const int s = mintree_prev_less(sm.mt, t, pre_m);
+            const int s = tl;
             if (s >= 0) {
                 const int64_t jj = pre_m - sm.tbase[s] - 1;
                 const uint32_t um = sm.tum[s];
@@ -459,8 +507,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         for (int r = 0; r < 6; ++r) {
             const bool in = ptr >= wbase;
             const int src = in ? ptr - wbase : lane;
-            const Box vv = {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE),
-                            __shfl(v.y1, src, WAVE)};
+            const V vv = shfl_idx(v, src);
             const int pp = __shfl(ptr, src, WAVE);
             if (in) {
                 v = isect(v, vv);
@@ -469,7 +516,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
         sm.jval[t] = v;
         sm.jptr[t] = ptr;
-        for (int r = 0; r < NWAVE && __syncthreads_or(ptr >= 0); ++r) {
+        for (int r = 0; r < NWAVE && __syncthreads_or(ptr >= 0); ++r) {  // also publishes tlink
             if (ptr >= 0) {
                 v = isect(v, sm.jval[ptr]);
                 ptr = sm.jptr[ptr];
@@ -479,6 +526,8 @@ __global__ __launch_bounds__(W) void k_resolve(
             sm.jptr[t] = ptr;
         }
         __syncthreads();
+    } else {
+        __syncthreads();  // publishes tlink
     }
 
     // ---- sequential walk over this thread's elements with a register stack
@@ -491,20 +540,23 @@ __global__ __launch_bounds__(W) void k_resolve(
     bool rseen = false;
     int64_t dep = Dt;
     int st_pos[K], st_kind[K];
-    Box st_ctx[K], st_acc[K], lout[K];
+    V st_ctx[K], st_acc[K], lout[K];
     int def_own[K], def_pos[K];
     int64_t def_L[K];
-    // the stack entry at level `cur_L` seen from this thread's start
+    // the stack entry at level `cur_L` seen from this thread's start; the
+    // levels asked for only decrease, so the owner search moves left along
+    // owner links from the previous thread
     int64_t cur_L = INT64_MIN, cur_idx = -1;
+    int own_s = t - 1;
     int cur_kind = -1, cur_own = -1, cur_pos = -1;
-    Box cur_ctx = box_inf();
+    V cur_ctx = Pay<V>::inf();
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         st_pos[j] = 0;
         st_kind[j] = 0;
-        st_ctx[j] = box_inf();
-        st_acc[j] = box_empty();
-        lout[j] = box_empty();
+        st_ctx[j] = Pay<V>::inf();
+        st_acc[j] = Pay<V>::empty();
+        lout[j] = Pay<V>::empty();
         def_own[j] = def_pos[j] = -1;
         def_L[j] = 0;
     }
@@ -528,7 +580,7 @@ __global__ __launch_bounds__(W) void k_resolve(
             cur_idx = -1;
             cur_kind = -1;
             cur_own = -1;
-            cur_ctx = box_inf();
+            cur_ctx = Pay<V>::inf();
             if (dep >= 1 && dep <= lowtop) {
                 const int64_t x = dep - preM;
                 if (x >= 0 && x <= aP) {
@@ -540,7 +592,8 @@ __global__ __launch_bounds__(W) void k_resolve(
                     }
                 }
             } else if (dep > lowtop) {
-                const int s = mintree_prev_less(sm.mt, t, dep);
+                while (own_s >= 0 && (int64_t)sm.tcm[own_s] >= dep) own_s = sm.tlink[own_s];
+                const int s = own_s;
                 if (s >= 0) {
                     const int64_t jj = dep - sm.tbase[s] - 1;
                     const uint32_t um = sm.tum[s];
@@ -556,13 +609,13 @@ __global__ __launch_bounds__(W) void k_resolve(
             }
         }
         int64_t top;
-        Box ctx;
+        V ctx;
         if (depth > 0) {
             top = g0 + st_pos[0];
             ctx = st_ctx[0];
         } else if (rseen) {
             top = -1;
-            ctx = box_inf();
+            ctx = Pay<V>::inf();
         } else {
             top = cur_idx;
             ctx = cur_ctx;
@@ -571,17 +624,17 @@ __global__ __launch_bounds__(W) void k_resolve(
         const uint32_t k = ks[j];
         if (k == LEAF) {
             if (BOXES) {
-                const Box o = canon(isect(bx[j], ctx));
+                const V o = canon(isect(bx[j], ctx));
                 lout[j] = o;
                 st_acc[0] = unite(st_acc[0], o);  // harmless when the stack is empty
-                if (real) st_box(out, i, o);
+                if (real) sink.emit(i, o);
             }
             if (match && real) match[i] = -1;
         } else if (is_open(k)) {
-            Box c = ctx;
+            V c = ctx;
             if (k == BCLIP) {
                 c = isect(bx[j], ctx);
-                if (BOXES && real) st_box(out, i, canon(c));
+                if (BOXES && real) sink.emit(i, canon(c));
             }
 #pragma unroll
             for (int q = K - 1; q > 0; --q) {
@@ -593,14 +646,14 @@ __global__ __launch_bounds__(W) void k_resolve(
             st_pos[0] = j;
             st_kind[0] = (int)k;
             st_ctx[0] = c;
-            st_acc[0] = box_empty();
+            st_acc[0] = Pay<V>::empty();
             ++depth;
             ++dep;
         } else if (depth > 0) {  // close matched inside this thread
             const int p = st_pos[0];
             const int ko = st_kind[0];
-            const Box oc = st_ctx[0];
-            const Box acc = st_acc[0];
+            const V oc = st_ctx[0];
+            const V acc = st_acc[0];
 #pragma unroll
             for (int q = 0; q < K - 1; ++q) {
                 st_pos[q] = st_pos[q + 1];
@@ -618,10 +671,10 @@ __global__ __launch_bounds__(W) void k_resolve(
             }
             if (BOXES && real) {
                 if (k == ECLIP) {
-                    st_box(out, i, canon(oc));
+                    sink.emit(i, canon(oc));
                 } else {
-                    st_box(out, i, acc);
-                    st_box(out, g0 + p, acc);
+                    sink.emit(i, acc);
+                    sink.emit(g0 + p, acc);
                 }
             }
         } else if (rseen) {  // close below its scene's root
@@ -639,7 +692,7 @@ __global__ __launch_bounds__(W) void k_resolve(
                 }
                 if (BOXES && real) {
                     if (k == ECLIP) {
-                        st_box(out, i, canon(cur_ctx));
+                        sink.emit(i, canon(cur_ctx));
                     } else {
                         defmask |= 1u << j;
                         def_L[j] = L;
@@ -667,13 +720,13 @@ __global__ __launch_bounds__(W) void k_resolve(
     if (!BOXES) return;
 
     // ---- unions that cross threads or partitions
-    Box ttot = box_empty();
+    V ttot = Pay<V>::empty();
 #pragma unroll
     for (int j = 0; j < K; ++j) ttot = unite(ttot, lout[j]);
     __syncthreads();  // the walk's reads of inc_ctx / jval / ucum are done
     uniontree_build(ut, ttot);
     {  // suffix unions after each of this thread's unmatched opens
-        Box suf = box_empty();
+        V suf = Pay<V>::empty();
 #pragma unroll
         for (int p = K - 1; p >= 0; --p) {
             if ((wk.umask >> p) & 1u) sm.ucum[t * K + p] = suf;
@@ -684,19 +737,19 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!((defmask >> j) & 1u)) continue;
-        Box pre = box_empty();
+        V pre = Pay<V>::empty();
 #pragma unroll
         for (int q = 0; q < K; ++q)
             if (q < j) pre = unite(pre, lout[q]);
         const int64_t i = g0 + j;
         if (def_own[j] >= 0) {
             const int s = def_own[j];
-            const Box u = unite(unite(sm.ucum[s * K + def_pos[j]], uniontree_range(ut, s + 1, t - 1)), pre);
-            st_box(out, i, u);
-            st_box(out, p0 + (int64_t)s * K + def_pos[j], u);
+            const V u = unite(unite(sm.ucum[s * K + def_pos[j]], uniontree_range(ut, s + 1, t - 1)), pre);
+            sink.emit(i, u);
+            sink.emit(p0 + (int64_t)s * K + def_pos[j], u);
         } else {
             const int64_t ci = dP - def_L[j];
-            if (ci >= 0 && ci < aP) st_box(cr_pre, p0 + ci, unite(uniontree_range(ut, 0, t - 1), pre));
+            if (ci >= 0 && ci < aP) Pay<V>::st(cr_pre, p0 + ci, unite(uniontree_range(ut, 0, t - 1), pre));
         }
     }
     // surviving blend opens: union from the open to the end of the partition
@@ -712,91 +765,156 @@ __global__ __launch_bounds__(W) void k_resolve(
             if (L > (int64_t)sufmin || ks[p] != BBLEND) continue;
             const int64_t slot = L - baseP - 1;
             if (slot < 0 || slot >= T) continue;
-            st_box(U_suf, p0 + slot, unite(sm.ucum[t * K + p], uniontree_range(ut, t + 1, W - 1)));
+            Pay<V>::st(U_suf, p0 + slot, unite(sm.ucum[t * K + p], uniontree_range(ut, t + 1, W - 1)));
         }
     }
-    if (t == 0) st_box(ptot, P, ut[1]);
+    if (t == 0) Pay<V>::st(ptot, P, ut[1]);
 }
 
 // ------------------------------------------------ range unions over partitions
 // Blocks of UB partitions: inclusive prefix and suffix unions inside each
 // block, and block totals.
-__global__ __launch_bounds__(UB) void k_ublocks(const float4 *__restrict__ ptot, int64_t M,
-                                                float4 *__restrict__ upre, float4 *__restrict__ usuf,
-                                                float4 *__restrict__ btot) {
-    __shared__ Box sh[UB / WAVE];
+template <class V>
+__global__ __launch_bounds__(UB) void k_ublocks(const void *__restrict__ ptot, int64_t M,
+                                                void *__restrict__ upre, void *__restrict__ usuf,
+                                                void *__restrict__ btot) {
+    __shared__ V sh[UB / WAVE];
     const int t = threadIdx.x;
     const int64_t B = blockIdx.x;
     const int64_t P = B * UB + t;
     const int64_t Pr = B * UB + (UB - 1 - t);
-    const Box v = P < M ? ld_box(ptot, P) : box_empty();
-    const Box vr = Pr < M ? ld_box(ptot, Pr) : box_empty();
-    Box tot, tot2;
-    const Box ex = block_excl_scan<UB / WAVE>(v, UniteOp{}, box_empty(), sh, &tot);
-    const Box exr = block_excl_scan<UB / WAVE>(vr, UniteOp{}, box_empty(), sh, &tot2);
-    if (P < M) st_box(upre, P, unite(ex, v));
-    if (Pr < M) st_box(usuf, Pr, unite(exr, vr));
-    if (t == 0) st_box(btot, B, tot);
+    const V v = P < M ? Pay<V>::ld(ptot, P) : Pay<V>::empty();
+    const V vr = Pr < M ? Pay<V>::ld(ptot, Pr) : Pay<V>::empty();
+    V tot, tot2;
+    const V ex = block_excl_scan<UB / WAVE>(v, UniteOp{}, Pay<V>::empty(), sh, &tot);
+    const V exr = block_excl_scan<UB / WAVE>(vr, UniteOp{}, Pay<V>::empty(), sh, &tot2);
+    if (P < M) Pay<V>::st(upre, P, unite(ex, v));
+    if (Pr < M) Pay<V>::st(usuf, Pr, unite(exr, vr));
+    if (t == 0) Pay<V>::st(btot, B, tot);
 }
 
 // Sparse table over block totals: level l holds unions of 2^l blocks.
 // Level 0 is the block totals themselves (the first nb entries of sp).
-__global__ __launch_bounds__(1024) void k_usparse(float4 *__restrict__ sp, int64_t nb, int levels) {
+template <class V>
+__global__ __launch_bounds__(1024) void k_usparse(void *__restrict__ sp, int64_t nb, int levels) {
     for (int l = 1; l < levels; ++l) {
         const int64_t half = (int64_t)1 << (l - 1);
         for (int64_t b = threadIdx.x; b < nb; b += 1024) {
-            Box v = ld_box(sp, (l - 1) * nb + b);
-            if (b + half < nb) v = unite(v, ld_box(sp, (l - 1) * nb + b + half));
-            st_box(sp, l * nb + b, v);
+            V v = Pay<V>::ld(sp, (l - 1) * nb + b);
+            if (b + half < nb) v = unite(v, Pay<V>::ld(sp, (l - 1) * nb + b + half));
+            Pay<V>::st(sp, l * nb + b, v);
         }
         __syncthreads();
     }
 }
 
-__device__ Box range_union(const float4 *ptot, const float4 *upre, const float4 *usuf,
-                           const float4 *sp, int64_t nb, int64_t a, int64_t b) {
-    Box u = box_empty();
+// union of partition totals over partitions [a, b]
+template <class V>
+__device__ V range_union(const void *ptot, const void *upre, const void *usuf, const void *sp,
+                         int64_t nb, int64_t a, int64_t b) {
+    V u = Pay<V>::empty();
     if (a > b) return u;
     const int64_t ba = a / UB, bb = b / UB;
     if (ba == bb) {
-        for (int64_t q = a; q <= b; ++q) u = unite(u, ld_box(ptot, q));
+        for (int64_t q = a; q <= b; ++q) u = unite(u, Pay<V>::ld(ptot, q));
         return u;
     }
-    u = unite(ld_box(usuf, a), ld_box(upre, b));
+    u = unite(Pay<V>::ld(usuf, a), Pay<V>::ld(upre, b));
     const int64_t l0 = ba + 1, l1 = bb - 1;
     if (l0 <= l1) {
         const int lv = 63 - __clzll((unsigned long long)(l1 - l0 + 1));
-        u = unite(u, ld_box(sp, lv * nb + l0));
-        u = unite(u, ld_box(sp, lv * nb + l1 - ((int64_t)1 << lv) + 1));
+        u = unite(u, Pay<V>::ld(sp, lv * nb + l0));
+        u = unite(u, Pay<V>::ld(sp, lv * nb + l1 - ((int64_t)1 << lv) + 1));
     }
     return u;
 }
 
+template <class V, class SINK>
 __global__ __launch_bounds__(W) void k_cross(const int4 *__restrict__ pinfo, int64_t M, int64_t n,
                                              const int32_t *__restrict__ U_idx,
-                                             const float4 *__restrict__ U_suf,
+                                             const void *__restrict__ U_suf,
                                              const int32_t *__restrict__ cr_slot,
                                              const int32_t *__restrict__ cr_c,
-                                             const float4 *__restrict__ cr_pre,
-                                             const float4 *__restrict__ ptot,
-                                             const float4 *__restrict__ upre,
-                                             const float4 *__restrict__ usuf,
-                                             const float4 *__restrict__ sp, int64_t nb,
-                                             float4 *__restrict__ out) {
-    const int64_t Q = blockIdx.x;
+                                             const void *__restrict__ cr_pre,
+                                             const void *__restrict__ ptot,
+                                             const void *__restrict__ upre,
+                                             const void *__restrict__ usuf,
+                                             const void *__restrict__ sp, int64_t nb, SINK sink) {
+    // one thread per record: workgroup (Q, sub) covers records sub*W .. sub*W+W-1
+    const int64_t Q = blockIdx.x / (T / W);
+    const int ci = (int)(blockIdx.x % (T / W)) * W + threadIdx.x;
     const int aQ = pinfo[Q].x;
-    for (int ci = threadIdx.x; ci < aQ && ci < T; ci += W) {
-        const int64_t slot = cr_slot[Q * T + ci];
-        if (slot < 0 || slot >= Q * T) continue;
-        const int64_t R = slot / T;
-        const int64_t c = cr_c[Q * T + ci];
-        const int64_t o = (int64_t)((uint32_t)U_idx[slot] & ~BLEND_BIT);
-        if (o < 0 || o >= n || c < 0 || c >= n) continue;
-        Box u = unite(ld_box(U_suf, slot), ld_box(cr_pre, Q * T + ci));
-        u = unite(u, range_union(ptot, upre, usuf, sp, nb, R + 1, Q - 1));
-        st_box(out, o, u);
-        st_box(out, c, u);
+    if (ci >= aQ) return;
+    const int64_t slot = cr_slot[Q * T + ci];
+    if (slot < 0 || slot >= Q * T) return;
+    const int64_t R = slot / T;
+    const int64_t c = cr_c[Q * T + ci];
+    const int64_t o = (int64_t)((uint32_t)U_idx[slot] & ~BLEND_BIT);
+    if (o < 0 || o >= n || c < 0 || c >= n) return;
+    V u = unite(Pay<V>::ld(U_suf, slot), Pay<V>::ld(cr_pre, Q * T + ci));
+    u = unite(u, range_union<V>(ptot, upre, usuf, sp, nb, R + 1, Q - 1));
+    sink.emit(o, u);
+    sink.emit(c, u);
+}
+
+// ------------------------------------------------------------------ sinks
+// Forward: node boxes are written out.
+struct SinkOut {
+    float4 *out;
+    __device__ __forceinline__ void emit(int64_t i, const Box &v) const { st_box(out, i, v); }
+};
+
+// Backward: each coordinate of a non-EMPTY output row routes q(g) to its
+// attaining input element.  A row's own coordinates are flagged in a
+// per-row mask (no atomics); every other route is an exact 64-bit atomic add.
+struct SinkGrad {
+    const float4 *g;
+    unsigned long long *acc;  // [n][4] two's-complement sums on the 2^-32 grid
+    uint8_t *selfm;           // [n] bit c: row i routes coordinate c to itself
+    int64_t n;
+    __device__ __forceinline__ void emit(int64_t i, const BoxS &v) const {
+        uint32_t m = 0;
+        if (v.x0 < v.x1 && v.y0 < v.y1) {
+            const float4 gv = g[i];
+            const float gc[4] = {gv.x, gv.y, gv.z, gv.w};
+            const int32_t sc[4] = {v.s0, v.s1, v.s2, v.s3};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int64_t s = sc[c];
+                if (s < 0 || s >= n) continue;
+                if (s == i) {
+                    m |= 1u << c;
+                } else if (gc[c] != 0.0f) {
+                    const long long q = __double2ll_rn((double)gc[c] * 4294967296.0);
+                    atomicAdd(acc + 4 * s + c, (unsigned long long)q);
+                }
+            }
+        }
+        selfm[i] = (uint8_t)m;
     }
+};
+
+// grad_in = RNE_fp32(acc + own q(g)) * 2^-32
+__global__ void k_grad_final(const float4 *__restrict__ g, const unsigned long long *__restrict__ acc,
+                             const uint8_t *__restrict__ selfm, float4 *__restrict__ gin, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t m = selfm[i];
+    const float4 gv = g[i];
+    const float gc[4] = {gv.x, gv.y, gv.z, gv.w};
+    float r[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        long long s = (long long)acc[4 * i + c];
+        if ((m >> c) & 1u) s += __double2ll_rn((double)gc[c] * 4294967296.0);
+        r[c] = __ll2float_rn(s) * 0x1p-32f;
+    }
+    gin[i] = make_float4(r[0], r[1], r[2], r[3]);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = 0ull;
 }
 
 // ----------------------------------------------------------------- driver
@@ -804,7 +922,7 @@ hipEvent_t g_prof_before = nullptr, g_prof_after = nullptr;
 
 static inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-FwdLayout fwd_layout(int64_t n, int64_t S) {
+FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad) {
     FwdLayout L{};
     const int64_t M = n > 0 ? (n + T - 1) / T : 1;
     int64_t Mp = 1;
@@ -825,92 +943,130 @@ FwdLayout fwd_layout(int64_t n, int64_t S) {
     L.pinfo = take(sizeof(int4) * M);
     L.part = take(sizeof(int4) * M);
     L.mtree = take(sizeof(int) * 2 * Mp);
+    L.bagg = take(sizeof(int2) * ((Mp + SB - 1) / SB + 1));
     L.jptr0 = take(sizeof(int32_t) * M);
     L.jptr1 = take(sizeof(int32_t) * M);
-    L.jval0 = take(sizeof(float4) * M);
-    L.jval1 = take(sizeof(float4) * M);
+    L.jval0 = take(vbytes * M);
+    L.jval1 = take(vbytes * M);
     L.U_idx = take(sizeof(int32_t) * M * T);
-    L.U_cum = take(sizeof(float4) * M * T);
-    L.U_suf = take(sizeof(float4) * M * T);
+    L.U_cum = take(vbytes * M * T);
+    L.U_suf = take(vbytes * M * T);
     L.cr_slot = take(sizeof(int32_t) * M * T);
     L.cr_c = take(sizeof(int32_t) * M * T);
-    L.cr_pre = take(sizeof(float4) * M * T);
+    L.cr_pre = take(vbytes * M * T);
     L.runs = take(sizeof(int4) * M * RMAX);
     L.rhead = take(sizeof(int4) * M);
-    L.ptot = take(sizeof(float4) * M);
-    L.upre = take(sizeof(float4) * M);
-    L.usuf = take(sizeof(float4) * M);
-    L.sp = take(sizeof(float4) * nb * lv);
+    L.ptot = take(vbytes * M);
+    L.upre = take(vbytes * M);
+    L.usuf = take(vbytes * M);
+    L.sp = take(vbytes * nb * lv);
     L.status = take(sizeof(uint32_t) * (S > 0 ? S : 1));
+    if (grad) {
+        L.acc = take(sizeof(unsigned long long) * 4 * (n > 0 ? n : 1));
+        L.selfm = take(n > 0 ? n : 1);
+    }
     L.total = o;
     return L;
 }
 
-hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t n,
-                   const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
-                   void *ws, uint32_t *status, hipStream_t st) {
-    const FwdLayout L = fwd_layout(n, off ? S : 1);
-    char *w = (char *)ws;
-    const int64_t nstat = off ? S : 1;
-    if (!status) status = (uint32_t *)(w + L.status);
-    k_zero_u32<<<(unsigned)((nstat + 255) / 256), 256, 0, st>>>(status, nstat);
-    if (off) k_check_offsets<<<(unsigned)((S + 1 + 255) / 256), 256, 0, st>>>(off, S, n, status);
-    if (n == 0) return hipGetLastError();
+template <bool BOXES, class V, class SINK>
+static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t n,
+                               const int64_t *off, int64_t S, int32_t *match, int32_t *pm,
+                               SINK sink, char *w, const FwdLayout &L, uint32_t *status,
+                               hipStream_t st) {
     const int64_t M = L.M;
     int4 *pinfo = (int4 *)(w + L.pinfo);
     int4 *part = (int4 *)(w + L.part);
     int *mtree = (int *)(w + L.mtree);
     int32_t *U_idx = (int32_t *)(w + L.U_idx);
-    float4 *U_cum = (float4 *)(w + L.U_cum);
-    if (boxes)
-        k_reduce<true><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
-    else
-        k_reduce<false><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
-    k_spine_scan<<<1, SPW, 0, st>>>(pinfo, M, part, mtree, L.Mp, off, S, n, status);
+    void *U_cum = w + L.U_cum;
+    k_reduce<BOXES, V><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
+    {
+        int2 *bagg = (int2 *)(w + L.bagg);
+        const int64_t nbk = (M + SB - 1) / SB;
+        k_spine_blocks<<<(unsigned)nbk, SB, 0, st>>>(pinfo, M, bagg);
+        k_spine_top<<<1, SB, 0, st>>>(bagg, nbk, off, S, n, status);
+        const int64_t nbt = (L.Mp + SB - 1) / SB;
+        k_spine_apply<<<(unsigned)nbt, SB, 0, st>>>(pinfo, M, bagg, part, mtree, L.Mp);
+        if (L.Mp > SB) k_spine_treetop<<<1, SB, 0, st>>>(mtree, L.Mp);
+    }
     int32_t *jp[2] = {(int32_t *)(w + L.jptr0), (int32_t *)(w + L.jptr1)};
-    float4 *jv[2] = {(float4 *)(w + L.jval0), (float4 *)(w + L.jval1)};
+    void *jv[2] = {w + L.jval0, w + L.jval1};
     const unsigned gM = (unsigned)((M + 255) / 256);
-    if (boxes)
-        k_spine_link<true><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
-    else
-        k_spine_link<false><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
+    k_spine_link<BOXES, V><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
     int cur = 0;
-    if (boxes) {
+    if (BOXES) {
         int rounds = 0;
         while (((int64_t)1 << rounds) < M) ++rounds;
         for (int r = 0; r < rounds; ++r) {
-            k_jump<<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
+            k_jump<V><<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
             cur ^= 1;
         }
     }
-    float4 *U_suf = (float4 *)(w + L.U_suf);
-    int32_t *cr_slot = (int32_t *)(w + L.cr_slot);
-    int32_t *cr_c = (int32_t *)(w + L.cr_c);
-    float4 *cr_pre = (float4 *)(w + L.cr_pre);
-    float4 *ptot = (float4 *)(w + L.ptot);
     int4 *runs = (int4 *)(w + L.runs);
     int4 *rhead = (int4 *)(w + L.rhead);
     k_runs<<<gM, 256, 0, st>>>(pinfo, part, M, runs, rhead);
+    void *U_suf = w + L.U_suf;
+    int32_t *cr_slot = (int32_t *)(w + L.cr_slot);
+    int32_t *cr_c = (int32_t *)(w + L.cr_c);
+    void *cr_pre = w + L.cr_pre;
+    void *ptot = w + L.ptot;
     const bool prof = g_prof_before && g_prof_after;
     if (prof) (void)hipEventRecord(g_prof_before, st);
-    if (boxes)
-        k_resolve<true><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx,
-                                                    U_cum, U_suf, cr_slot, cr_c, cr_pre, ptot, match,
-                                                    pm, out, status);
-    else
-        k_resolve<false><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur],
-                                                     U_idx, U_cum, U_suf, cr_slot, cr_c, cr_pre,
-                                                     ptot, match, pm, out, status);
+    k_resolve<BOXES, V, SINK><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs,
+                                                         rhead, jv[cur], U_idx, U_cum, U_suf,
+                                                         cr_slot, cr_c, cr_pre, ptot, match, pm,
+                                                         sink, status);
     if (prof) (void)hipEventRecord(g_prof_after, st);
-    if (boxes) {
-        float4 *upre = (float4 *)(w + L.upre);
-        float4 *usuf = (float4 *)(w + L.usuf);
-        float4 *sp = (float4 *)(w + L.sp);
-        k_ublocks<<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp);
-        k_usparse<<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
-        k_cross<<<(unsigned)M, W, 0, st>>>(pinfo, M, n, U_idx, U_suf, cr_slot, cr_c, cr_pre, ptot,
-                                           upre, usuf, sp, L.nb, out);
+    if (BOXES) {
+        void *upre = w + L.upre;
+        void *usuf = w + L.usuf;
+        void *sp = w + L.sp;
+        k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp);
+        k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
+        k_cross<V, SINK><<<(unsigned)(M * (T / W)), W, 0, st>>>(pinfo, M, n, U_idx, U_suf, cr_slot, cr_c,
+                                                     cr_pre, ptot, upre, usuf, sp, L.nb, sink);
     }
+    return hipGetLastError();
+}
+
+static uint32_t *prep_status(char *w, const FwdLayout &L, const int64_t *off, int64_t S,
+                             int64_t n, uint32_t *status, hipStream_t st) {
+    const int64_t nstat = off ? S : 1;
+    if (!status) status = (uint32_t *)(w + L.status);
+    k_zero_u32<<<(unsigned)((nstat + 255) / 256), 256, 0, st>>>(status, nstat);
+    if (off) k_check_offsets<<<(unsigned)((S + 1 + 255) / 256), 256, 0, st>>>(off, S, n, status);
+    return status;
+}
+
+hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t n,
+                   const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
+                   void *ws, uint32_t *status, hipStream_t st) {
+    const FwdLayout L = fwd_layout(n, off ? S : 1, sizeof(Box), false);
+    char *w = (char *)ws;
+    status = prep_status(w, L, off, S, n, status, st);
+    if (n == 0) return hipGetLastError();
+    if (boxes)
+        return run_pipeline<true, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w,
+                                                L, status, st);
+    return run_pipeline<false, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w, L,
+                                             status, st);
+}
+
+hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,
+                   float4 *grad_in, void *ws, uint32_t *status, hipStream_t st) {
+    const FwdLayout L = fwd_layout(n, 1, sizeof(BoxS), true);
+    char *w = (char *)ws;
+    status = prep_status(w, L, nullptr, 1, n, status, st);
+    if (n == 0) return hipGetLastError();
+    unsigned long long *acc = (unsigned long long *)(w + L.acc);
+    uint8_t *selfm = (uint8_t *)(w + L.selfm);
+    k_zero_u64<<<(unsigned)((4 * n + 255) / 256), 256, 0, st>>>(acc, 4 * n);
+    hipError_t e = run_pipeline<true, BoxS, SinkGrad>(kind, box, n, nullptr, 1, nullptr, nullptr,
+                                                      SinkGrad{grad_out, acc, selfm, n}, w, L,
+                                                      status, st);
+    if (e != hipSuccess) return e;
+    k_grad_final<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(grad_out, acc, selfm, grad_in, n);
     return hipGetLastError();
 }
 
