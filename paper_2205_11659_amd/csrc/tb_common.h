@@ -158,6 +158,27 @@ __device__ __forceinline__ Seg shfl_up(Seg s, int d) { return {shfl_up(s.r, d), 
 struct SegOp {
     __device__ Seg operator()(Seg x, Seg y) const { return y.r ? y : Seg{x.r, x.v + y.v}; }
 };
+// Bicyclic element with scene resets: (a pops of the stack below, b
+// unmatched opens left, r a reset occurred).  (a,b) ⊕ (c,d) is the paper's
+// bicyclic product; a reset clears what lies to its left, so pops after it
+// never reach further down.
+struct BicR {
+    int a, b, r;
+};
+__device__ __forceinline__ BicR shfl_up(BicR x, int d) {
+    return {shfl_up(x.a, d), shfl_up(x.b, d), shfl_up(x.r, d)};
+}
+__device__ __forceinline__ BicR bicr(const BicR &x, const BicR &y) {
+    const int m = x.b < y.a ? x.b : y.a;
+    return {x.a + (x.r ? 0 : y.a - m), y.r ? y.b : x.b + y.b - m, x.r | y.r};
+}
+struct BicROp {
+    __device__ BicR operator()(BicR x, BicR y) const { return bicr(x, y); }
+};
+// the same product with its operands swapped, for scans run right to left
+struct BicRRevOp {
+    __device__ BicR operator()(BicR x, BicR y) const { return bicr(y, x); }
+};
 struct MinOp {
     __device__ int operator()(int a, int b) const { return a < b ? a : b; }
 };

@@ -57,10 +57,8 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
                                               const int64_t *__restrict__ off, int64_t S,
                                               int4 *__restrict__ pinfo,
                                               int32_t *__restrict__ U_idx, void *__restrict__ U_cum) {
-    __shared__ Seg sh_seg[NWAVE];
-    __shared__ int sh_i[NWAVE];
+    __shared__ BicR sh_bic[NWAVE];
     __shared__ V sh_b[NWAVE];
-    __shared__ int mt[2 * W];
     const int t = threadIdx.x;
     const int64_t P = blockIdx.x;
     const int64_t g0 = P * T + (int64_t)t * K;
@@ -72,29 +70,27 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
         if (ks[j] > 4u) ks[j] = LEAF;
     const uint32_t rm = reset_mask(off, S, g0);
     const Walk wk = walk_kinds(ks, rm);
-    const int b = __popc(wk.umask);
+    const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
 
-    Seg tot;
-    const Seg ex = block_excl_scan<NWAVE>(Seg{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a}, SegOp{},
-                                          Seg{0, 0}, sh_seg, &tot);
-    const int D = ex.v;  // depth at thread start: partition-relative unless ex.r
-    const int cm = wk.rs ? SENT : D - wk.a;
+    // prefix: depth at this thread's start; total: the partition's summary
+    BicR tot;
+    const BicR pre = block_excl_scan<NWAVE>(mine, BicROp{}, BicR{0, 0, 0}, sh_bic, &tot);
+    const int D = pre.r ? pre.b : pre.b - pre.a;  // partition-relative unless a reset came first
     const int base = wk.rs ? 0 : D - wk.a;
-    // pops below the partition start happen only before the first reset
-    int lo_tot;
-    block_excl_scan<NWAVE>(ex.r ? INT32_MAX : D - wk.a, MinOp{}, INT32_MAX, sh_i, &lo_tot);
-    const int aP = lo_tot < 0 ? -lo_tot : 0;
-    int rcount;
-    block_excl_scan<NWAVE>(wk.rs ? 1 : 0, AddOp{}, 0, sh_i, &rcount);
-    const bool rP = rcount > 0;
-    const int baseP = rP ? 0 : -aP;
-
-    // an unmatched open at level L survives the partition unless a later
-    // thread's lowest level is below L
-    mintree_build(mt, cm);
-    const int sufmin = mintree_range_min(mt, t + 1, W - 1);
-    int ns = 0;
-    if ((int64_t)sufmin > (int64_t)base) ns = (int)min((int64_t)b, (int64_t)sufmin - base);
+    const int baseP = tot.r ? 0 : -tot.a;
+    // suffix (later threads): how many of this thread's unmatched opens they
+    // pop.  Thread t scans the value of thread W-1-t with the swapped
+    // product, so it ends up holding the product over threads after W-1-t.
+    __shared__ BicR xch[W];
+    xch[t] = mine;
+    __syncthreads();
+    BicR rtot;
+    const BicR suf_r = block_excl_scan<NWAVE>(xch[W - 1 - t], BicRRevOp{}, BicR{0, 0, 0}, sh_bic, &rtot);
+    xch[W - 1 - t] = suf_r;  // every read of xch happened before the scan's barriers
+    __syncthreads();
+    const BicR suf = xch[t];
+    const int b = mine.b;
+    const int ns = suf.r ? 0 : (b > suf.a ? b - suf.a : 0);
 
     V agg = Pay<V>::inf(), bxs[K];
     uint32_t clipmask = 0;
@@ -115,8 +111,6 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
     }
     V aggtot;
     V cum = BOXES ? block_excl_scan<NWAVE>(agg, IsectOp{}, Pay<V>::inf(), sh_b, &aggtot) : Pay<V>::inf();
-    int nsum;
-    block_excl_scan<NWAVE>(ns, AddOp{}, 0, sh_i, &nsum);
 
     int jj = 0;
 #pragma unroll
@@ -135,7 +129,7 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
         }
         ++jj;
     }
-    if (t == 0) pinfo[P] = make_int4(aP, nsum, rP ? 1 : 0, 0);
+    if (t == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
 }
 
 // ------------------------------------------------------------ spine kernels
