@@ -194,6 +194,11 @@ struct UniteOp {
     __device__ V operator()(V a, V b) const { return unite(a, b); }
 };
 
+__device__ __forceinline__ BicR shfl_idx(BicR x, int src) {
+    return {__shfl(x.a, src, WAVE), __shfl(x.b, src, WAVE), __shfl(x.r, src, WAVE)};
+}
+__device__ __forceinline__ int shfl_idx(int x, int src) { return __shfl(x, src, WAVE); }
+
 template <class V, class Op>
 __device__ __forceinline__ V wave_incl_scan(V v, Op op) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -203,6 +208,17 @@ __device__ __forceinline__ V wave_incl_scan(V v, Op op) {
         if (lane >= o) v = op(u, v);
     }
     return v;
+}
+
+// Exclusive scan inside one wave; also returns the wave total.
+template <class V, class Op>
+__device__ __forceinline__ V wave_excl_scan(V v, Op op, V ident, V *total) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const V inc = wave_incl_scan(v, op);
+    *total = shfl_idx(inc, WAVE - 1);
+    V ex = shfl_up(inc, 1);
+    if (lane == 0) ex = ident;
+    return ex;
 }
 
 // Exclusive scan over the NW*64 threads of a workgroup; `sh` holds NW values.
@@ -229,10 +245,11 @@ __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *tota
 // ----------------------------------------------------------- small helpers
 __device__ __forceinline__ int msb32(uint32_t x) { return 31 - __clz(x); }
 
-// position of the j-th (0-based) set bit of a K-bit mask, or -1
+// position of the j-th (0-based) set bit of a KK-bit mask, or -1
+template <int KK = K>
 __device__ __forceinline__ int nth_bit(uint32_t mask, int j) {
 #pragma unroll
-    for (int p = 0; p < K; ++p) {
+    for (int p = 0; p < KK; ++p) {
         if ((mask >> p) & 1u) {
             if (j == 0) return p;
             --j;
@@ -278,14 +295,15 @@ __device__ __forceinline__ int64_t scene_of(const int64_t *off, int64_t S, int64
     return s < 0 ? 0 : (s >= S ? S - 1 : s);
 }
 
-// Scene starts inside [g0, g0+K) as a bit mask (bit j: element g0+j starts a
+// Scene starts inside [g0, g0+KK) as a bit mask (bit j: element g0+j starts a
 // scene).  Without offsets the only start is element 0.
+template <int KK = K>
 __device__ __forceinline__ uint32_t reset_mask(const int64_t *off, int64_t S, int64_t g0) {
     if (!off) return g0 == 0 ? 1u : 0u;
     uint32_t r = 0;
     for (int64_t s = lower_bound64(off, S + 1, g0); s <= S; ++s) {
         int64_t o = off[s];
-        if (o >= g0 + K) break;
+        if (o >= g0 + KK) break;
         if (o >= g0) r |= 1u << (o - g0);
     }
     return r;
@@ -296,15 +314,20 @@ __device__ __forceinline__ void flag(uint32_t *status, const int64_t *off, int64
     atomicOr(status + scene_of(off, S, i), bits);
 }
 
-// Loads K kinds of one thread; elements at or past n read as LEAF.
+// Loads KK kinds of one thread; elements at or past n read as LEAF.
+template <int KK>
 __device__ __forceinline__ void load_kinds(const uint32_t *kind, int64_t n, int64_t g0,
-                                           uint32_t (&ks)[K]) {
-    if (g0 + K <= n) {
-        uint4 v = *reinterpret_cast<const uint4 *>(kind + g0);
-        ks[0] = v.x, ks[1] = v.y, ks[2] = v.z, ks[3] = v.w;
+                                           uint32_t (&ks)[KK]) {
+    static_assert(KK % 4 == 0, "kinds load in groups of four");
+    if (g0 + KK <= n) {
+#pragma unroll
+        for (int q = 0; q < KK / 4; ++q) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(kind + g0 + 4 * q);
+            ks[4 * q] = v.x, ks[4 * q + 1] = v.y, ks[4 * q + 2] = v.z, ks[4 * q + 3] = v.w;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j) ks[j] = (g0 + j < n) ? kind[g0 + j] : LEAF;
+        for (int j = 0; j < KK; ++j) ks[j] = (g0 + j < n) ? kind[g0 + j] : LEAF;
     }
 }
 
@@ -317,12 +340,13 @@ struct Walk {
     uint32_t umask;
     bool rs;
 };
-__device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[K], uint32_t rm) {
+template <int KK>
+__device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[KK], uint32_t rm) {
     uint32_t mask = 0;
     int a = 0;
     bool rs = false;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < KK; ++j) {
         if ((rm >> j) & 1u) {
             mask = 0;
             rs = true;

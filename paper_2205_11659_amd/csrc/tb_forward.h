@@ -11,9 +11,9 @@ namespace tb {
 struct FwdLayout {
     int64_t M, Mp, nb;
     int levels;
-    size_t pinfo, part, mtree, bagg, jptr0, jptr1, jval0, jval1;
+    size_t pinfo, part, mtree, bagg, crbase, crtot, jptr0, jptr1, jval0, jval1;
     size_t U_idx, U_cum, U_suf, cr_slot, cr_c, cr_pre;
-    size_t runs, rhead, ptot, upre, usuf, sp, status, acc, selfm;
+    size_t runs, rhead, ptot, upre, usuf, sp, spb, status, acc, selfm;
     size_t total;
 };
 

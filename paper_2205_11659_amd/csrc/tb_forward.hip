@@ -51,70 +51,83 @@ __global__ void k_check_offsets(const int64_t *off, int64_t S, int64_t n, uint32
 }
 
 // ---------------------------------------------------------------- k_reduce
-template <bool BOXES, class V>
-__global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
-                                              const float4 *__restrict__ box, int64_t n,
-                                              const int64_t *__restrict__ off, int64_t S,
-                                              int4 *__restrict__ pinfo,
-                                              int32_t *__restrict__ U_idx, void *__restrict__ U_cum) {
-    __shared__ BicR sh_bic[NWAVE];
-    __shared__ V sh_b[NWAVE];
-    const int t = threadIdx.x;
-    const int64_t P = blockIdx.x;
-    const int64_t g0 = P * T + (int64_t)t * K;
+// One wave per partition: each lane walks RK = T / 64 consecutive elements,
+// so every combine below is a wave-level shuffle scan (no LDS, no barrier).
+// A workgroup holds RW independent waves.
+constexpr int RK = T / WAVE;
+constexpr int RW = 4;
 
-    uint32_t ks[K];
-    load_kinds(kind, n, g0, ks);
+template <bool BOXES, class V>
+__global__ __launch_bounds__(RW * WAVE) void k_reduce(const uint32_t *__restrict__ kind,
+                                                 const float4 *__restrict__ box, int64_t n,
+                                                 const int64_t *__restrict__ off, int64_t S,
+                                                 int4 *__restrict__ pinfo,
+                                                 int32_t *__restrict__ U_idx,
+                                                 void *__restrict__ U_cum) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t P = (int64_t)blockIdx.x * RW + (threadIdx.x >> 6);
+    const int64_t M = (n + T - 1) / T;
+    if (P >= M) return;  // whole wave leaves: no shuffle below sees it
+    const int64_t g0 = P * T + (int64_t)lane * RK;
+
+    uint32_t ks[RK];
+    load_kinds<RK>(kind, n, g0, ks);
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+    for (int j = 0; j < RK; ++j)
         if (ks[j] > 4u) ks[j] = LEAF;
-    const uint32_t rm = reset_mask(off, S, g0);
-    const Walk wk = walk_kinds(ks, rm);
+    const uint32_t rm = reset_mask<RK>(off, S, g0);
+    const Walk wk = walk_kinds<RK>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
 
-    // prefix: depth at this thread's start; total: the partition's summary
+    // prefix: depth at this lane's start; total: the partition's summary
     BicR tot;
-    const BicR pre = block_excl_scan<NWAVE>(mine, BicROp{}, BicR{0, 0, 0}, sh_bic, &tot);
+    const BicR pre = wave_excl_scan(mine, BicROp{}, BicR{0, 0, 0}, &tot);
     const int D = pre.r ? pre.b : pre.b - pre.a;  // partition-relative unless a reset came first
     const int base = wk.rs ? 0 : D - wk.a;
     const int baseP = tot.r ? 0 : -tot.a;
-    // suffix (later threads): how many of this thread's unmatched opens they
-    // pop.  Thread t scans the value of thread W-1-t with the swapped
-    // product, so it ends up holding the product over threads after W-1-t.
-    __shared__ BicR xch[W];
-    xch[t] = mine;
-    __syncthreads();
-    BicR rtot;
-    const BicR suf_r = block_excl_scan<NWAVE>(xch[W - 1 - t], BicRRevOp{}, BicR{0, 0, 0}, sh_bic, &rtot);
-    xch[W - 1 - t] = suf_r;  // every read of xch happened before the scan's barriers
-    __syncthreads();
-    const BicR suf = xch[t];
+    // suffix (later lanes): how many of this lane's unmatched opens they pop.
+    // Lane l scans lane 63-l's value with the swapped product, then hands the
+    // result back.
+    BicR rt;
+    const BicR rsuf = wave_excl_scan(shfl_idx(mine, WAVE - 1 - lane), BicRRevOp{}, BicR{0, 0, 0}, &rt);
+    const BicR suf = shfl_idx(rsuf, WAVE - 1 - lane);
     const int b = mine.b;
     const int ns = suf.r ? 0 : (b > suf.a ? b - suf.a : 0);
 
-    V agg = Pay<V>::inf(), bxs[K];
-    uint32_t clipmask = 0;
-    if (BOXES) {
+    // boxes of the surviving clip opens: all gathers are issued before any is used
+    uint32_t need = 0;
+    {
         int jj = 0;
 #pragma unroll
-        for (int p = 0; p < K; ++p) {
-            bxs[p] = Pay<V>::inf();
+        for (int p = 0; p < RK; ++p) {
             if ((wk.umask >> p) & 1u) {
-                if (jj < ns && ks[p] == BCLIP) {
-                    bxs[p] = Pay<V>::own(box[g0 + p], g0 + p);
-                    agg = isect(agg, bxs[p]);
-                    clipmask |= 1u << p;
-                }
+                if (jj < ns && ks[p] == BCLIP) need |= 1u << p;
                 ++jj;
             }
         }
     }
+    V bxs[RK];
+    if (BOXES) {
+#pragma unroll
+        for (int p = 0; p < RK; ++p) {
+            float4 f = make_float4(-INFINITY, -INFINITY, INFINITY, INFINITY);
+            if ((need >> p) & 1u) f = box[g0 + p];
+            bxs[p] = Pay<V>::own(f, g0 + p);
+        }
+    }
+    // intersection of the surviving clip opens, then its exclusive prefix over lanes
+    V agg = Pay<V>::inf();
+    if (BOXES) {
+#pragma unroll
+        for (int p = 0; p < RK; ++p)
+            if ((need >> p) & 1u) agg = isect(agg, bxs[p]);
+    }
     V aggtot;
-    V cum = BOXES ? block_excl_scan<NWAVE>(agg, IsectOp{}, Pay<V>::inf(), sh_b, &aggtot) : Pay<V>::inf();
+    V cum = BOXES ? wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &aggtot) : Pay<V>::inf();
 
     int jj = 0;
 #pragma unroll
-    for (int p = 0; p < K; ++p) {
+    for (int p = 0; p < RK; ++p) {
         if (!((wk.umask >> p) & 1u)) continue;
         if (jj < ns) {
             const int64_t L = (int64_t)base + 1 + jj;
@@ -122,14 +135,14 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
             if (slot >= 0 && slot < T) {
                 U_idx[P * T + slot] = (int32_t)((uint32_t)(g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
                 if (BOXES) {
-                    if ((clipmask >> p) & 1u) cum = isect(cum, bxs[p]);
+                    if ((need >> p) & 1u) cum = isect(cum, bxs[p]);
                     Pay<V>::st(U_cum, P * T + slot, cum);
                 }
             }
         }
         ++jj;
     }
-    if (t == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
+    if (lane == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
 }
 
 // ------------------------------------------------------------ spine kernels
@@ -142,49 +155,65 @@ constexpr int SB = 1024;
 __device__ __forceinline__ Seg part_seg(int4 v) { return Seg{v.z, v.z ? v.y : v.y - v.x}; }
 
 __global__ __launch_bounds__(SB) void k_spine_blocks(const int4 *__restrict__ pinfo, int64_t M,
-                                                     int2 *__restrict__ bagg) {
+                                                     int4 *__restrict__ bagg) {
     __shared__ Seg sh[SB / WAVE];
+    __shared__ int shi[SB / WAVE];
     const int64_t P = (int64_t)blockIdx.x * SB + threadIdx.x;
-    const Seg v = P < M ? part_seg(pinfo[P]) : Seg{0, 0};
+    const int4 pv = P < M ? pinfo[P] : make_int4(0, 0, 0, 0);
+    const Seg v = P < M ? part_seg(pv) : Seg{0, 0};
     Seg tot;
     block_excl_scan<SB / WAVE>(v, SegOp{}, Seg{0, 0}, sh, &tot);
-    if (threadIdx.x == 0) bagg[blockIdx.x] = make_int2(tot.r, tot.v);
+    int atot;
+    block_excl_scan<SB / WAVE>(pv.x, AddOp{}, 0, shi, &atot);
+    if (threadIdx.x == 0) bagg[blockIdx.x] = make_int4(tot.r, tot.v, atot, 0);
 }
 
 // exclusive scan of the block totals (nbk <= SB * SPT), in place; checks
 // that the whole sequence ends at depth 0
 constexpr int SPT = 4;
-__global__ __launch_bounds__(SB) void k_spine_top(int2 *__restrict__ bagg, int64_t nbk,
+__global__ __launch_bounds__(SB) void k_spine_top(int4 *__restrict__ bagg, int64_t nbk,
                                                   const int64_t *__restrict__ off, int64_t S,
-                                                  int64_t n, uint32_t *__restrict__ status) {
+                                                  int64_t n, uint32_t *__restrict__ status,
+                                                  int *__restrict__ crtot) {
     __shared__ Seg sh[SB / WAVE];
+    __shared__ int shi[SB / WAVE];
     const int t = threadIdx.x;
     Seg v[SPT], agg{0, 0};
+    int av[SPT], aagg = 0;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
         const int64_t b = (int64_t)t * SPT + q;
-        const int2 x = b < nbk ? bagg[b] : make_int2(0, 0);
+        const int4 x = b < nbk ? bagg[b] : make_int4(0, 0, 0, 0);
         v[q] = Seg{x.x, x.y};
+        av[q] = x.z;
         agg = SegOp{}(agg, v[q]);
+        aagg += x.z;
     }
     Seg tot;
     Seg ex = block_excl_scan<SB / WAVE>(agg, SegOp{}, Seg{0, 0}, sh, &tot);
+    int atot;
+    int aex = block_excl_scan<SB / WAVE>(aagg, AddOp{}, 0, shi, &atot);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
         const int64_t b = (int64_t)t * SPT + q;
-        if (b < nbk) bagg[b] = make_int2(ex.r, ex.v);
+        if (b < nbk) bagg[b] = make_int4(ex.r, ex.v, aex, 0);
         ex = SegOp{}(ex, v[q]);
+        aex += av[q];
     }
-    if (t == 0 && tot.v != 0 && n > 0) flag(status, off, S, n - 1, ST_UNBAL);
+    if (t == 0) {
+        *crtot = atot;
+        if (tot.v != 0 && n > 0) flag(status, off, S, n - 1, ST_UNBAL);
+    }
 }
 
 // blocks cover [0, Mp): partition records, min-tree leaves and the block's
 // subtree (padding leaves hold INT32_MAX)
 __global__ __launch_bounds__(SB) void k_spine_apply(const int4 *__restrict__ pinfo, int64_t M,
-                                                    const int2 *__restrict__ bex,
+                                                    const int4 *__restrict__ bex,
                                                     int4 *__restrict__ part, int *__restrict__ mtree,
-                                                    int64_t Mp) {
+                                                    int64_t Mp, int *__restrict__ crbase) {
     __shared__ Seg sh[SB / WAVE];
+    __shared__ int shi[SB / WAVE];
     __shared__ int lt[SB];
     const int t = threadIdx.x;
     const int64_t B = blockIdx.x;
@@ -193,9 +222,12 @@ __global__ __launch_bounds__(SB) void k_spine_apply(const int4 *__restrict__ pin
     const Seg v = P < M ? part_seg(pv) : Seg{0, 0};
     Seg tot;
     const Seg loc = block_excl_scan<SB / WAVE>(v, SegOp{}, Seg{0, 0}, sh, &tot);
+    int atot;
+    const int aloc = block_excl_scan<SB / WAVE>(P < M ? pv.x : 0, AddOp{}, 0, shi, &atot);
     int cm = INT32_MAX;
     if (P < M) {
-        const int2 bx = bex[B];
+        const int4 bx = bex[B];
+        crbase[P] = bx.z + aloc;
         const Seg ex = SegOp{}(Seg{bx.x, bx.y}, loc);
         const int d = ex.v;
         const int pre_m = d - pv.x;
@@ -388,9 +420,10 @@ __global__ __launch_bounds__(W) void k_resolve(
     const int4 *__restrict__ part, const int4 *__restrict__ runs_g,
     const int4 *__restrict__ rhead_g, const void *__restrict__ base_ctx,
     const int32_t *__restrict__ U_idx, const void *__restrict__ U_cum,
-    void *__restrict__ U_suf, int32_t *__restrict__ cr_slot, int32_t *__restrict__ cr_c,
-    void *__restrict__ cr_pre, void *__restrict__ ptot, int32_t *__restrict__ match,
-    int32_t *__restrict__ pm, SINK sink, uint32_t *__restrict__ status) {
+    void *__restrict__ U_suf, const int *__restrict__ crbase, int32_t *__restrict__ cr_slot,
+    int32_t *__restrict__ cr_c, void *__restrict__ cr_pre, void *__restrict__ ptot,
+    int32_t *__restrict__ match, int32_t *__restrict__ pm, SINK sink,
+    uint32_t *__restrict__ status) {
     __shared__ ResolveSmem<BOXES, V> sm;
     V *ut = sm.inc_ctx;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
@@ -403,10 +436,11 @@ __global__ __launch_bounds__(W) void k_resolve(
     const int64_t preM = dP - aP;  // lowest incoming level any element here can see
     const int4 head = rhead_g[P];
     const int nruns = head.x;
+    const int64_t rbase = crbase[P];  // this partition's close records start here
 
     // ---- loads: inputs, owner runs
     uint32_t kr[K], ks[K];
-    load_kinds(kind, n, g0, kr);
+    load_kinds<K>(kind, n, g0, kr);
     V bx[K];
     if (BOXES) {
 #pragma unroll
@@ -437,7 +471,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
 
     // ---- per-thread walk and thread-level depths
-    const Walk wk = walk_kinds(ks, rm);
+    const Walk wk = walk_kinds<K>(ks, rm);
     const int b = __popc(wk.umask);
     Seg segtot;
     const Seg ex = block_excl_scan<NWAVE>(Seg{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a}, SegOp{},
@@ -704,8 +738,8 @@ __global__ __launch_bounds__(W) void k_resolve(
                         int64_t R;
                         sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, &R);
                     }
-                    cr_slot[p0 + ci] = sl;
-                    cr_c[p0 + ci] = (int32_t)i;
+                    cr_slot[rbase + ci] = sl;
+                    cr_c[rbase + ci] = (int32_t)i;
                 }
             }
             --dep;
@@ -743,7 +777,7 @@ __global__ __launch_bounds__(W) void k_resolve(
             sink.emit(p0 + (int64_t)s * K + def_pos[j], u);
         } else {
             const int64_t ci = dP - def_L[j];
-            if (ci >= 0 && ci < aP) Pay<V>::st(cr_pre, p0 + ci, unite(uniontree_range(ut, 0, t - 1), pre));
+            if (ci >= 0 && ci < aP) Pay<V>::st(cr_pre, rbase + ci, unite(uniontree_range(ut, 0, t - 1), pre));
         }
     }
     // surviving blend opens: union from the open to the end of the partition
@@ -767,12 +801,15 @@ __global__ __launch_bounds__(W) void k_resolve(
 
 // ------------------------------------------------ range unions over partitions
 // Blocks of UB partitions: inclusive prefix and suffix unions inside each
-// block, and block totals.
+// block, block totals, and an in-block sparse table (level l at partition q
+// holds the union of partitions q .. q+2^l-1, clipped to the block).
+constexpr int UBL = 8;  // log2(UB)
 template <class V>
 __global__ __launch_bounds__(UB) void k_ublocks(const void *__restrict__ ptot, int64_t M,
                                                 void *__restrict__ upre, void *__restrict__ usuf,
-                                                void *__restrict__ btot) {
+                                                void *__restrict__ btot, void *__restrict__ spb) {
     __shared__ V sh[UB / WAVE];
+    __shared__ V lv[UB];
     const int t = threadIdx.x;
     const int64_t B = blockIdx.x;
     const int64_t P = B * UB + t;
@@ -785,6 +822,17 @@ __global__ __launch_bounds__(UB) void k_ublocks(const void *__restrict__ ptot, i
     if (P < M) Pay<V>::st(upre, P, unite(ex, v));
     if (Pr < M) Pay<V>::st(usuf, Pr, unite(exr, vr));
     if (t == 0) Pay<V>::st(btot, B, tot);
+    V cur = v;
+    lv[t] = cur;
+    if (P < M) Pay<V>::st(spb, P, cur);
+    for (int l = 1; l < UBL; ++l) {
+        __syncthreads();
+        const int h = 1 << (l - 1);
+        if (t + h < UB) cur = unite(cur, lv[t + h]);
+        __syncthreads();
+        lv[t] = cur;
+        if (P < M) Pay<V>::st(spb, (int64_t)l * M + P, cur);
+    }
 }
 
 // Sparse table over block totals: level l holds unions of 2^l blocks.
@@ -802,15 +850,17 @@ __global__ __launch_bounds__(1024) void k_usparse(void *__restrict__ sp, int64_t
     }
 }
 
-// union of partition totals over partitions [a, b]
+// union of partition totals over partitions [a, b]: O(1) loads
 template <class V>
-__device__ V range_union(const void *ptot, const void *upre, const void *usuf, const void *sp,
-                         int64_t nb, int64_t a, int64_t b) {
+__device__ V range_union(const void *upre, const void *usuf, const void *sp, const void *spb,
+                         int64_t M, int64_t nb, int64_t a, int64_t b) {
     V u = Pay<V>::empty();
     if (a > b) return u;
     const int64_t ba = a / UB, bb = b / UB;
     if (ba == bb) {
-        for (int64_t q = a; q <= b; ++q) u = unite(u, Pay<V>::ld(ptot, q));
+        // levels stop at 2^(UBL-1): two spans of that length cover a whole block
+        const int lv = min(63 - __clzll((unsigned long long)(b - a + 1)), UBL - 1);
+        u = unite(Pay<V>::ld(spb, lv * M + a), Pay<V>::ld(spb, lv * M + b - ((int64_t)1 << lv) + 1));
         return u;
     }
     u = unite(Pay<V>::ld(usuf, a), Pay<V>::ld(upre, b));
@@ -824,31 +874,47 @@ __device__ V range_union(const void *ptot, const void *upre, const void *usuf, c
 }
 
 template <class V, class SINK>
-__global__ __launch_bounds__(W) void k_cross(const int4 *__restrict__ pinfo, int64_t M, int64_t n,
+__global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int64_t n,
                                              const int32_t *__restrict__ U_idx,
                                              const void *__restrict__ U_suf,
                                              const int32_t *__restrict__ cr_slot,
                                              const int32_t *__restrict__ cr_c,
                                              const void *__restrict__ cr_pre,
-                                             const void *__restrict__ ptot,
                                              const void *__restrict__ upre,
                                              const void *__restrict__ usuf,
-                                             const void *__restrict__ sp, int64_t nb, SINK sink) {
-    // one thread per record: workgroup (Q, sub) covers records sub*W .. sub*W+W-1
-    const int64_t Q = blockIdx.x / (T / W);
-    const int ci = (int)(blockIdx.x % (T / W)) * W + threadIdx.x;
-    const int aQ = pinfo[Q].x;
-    if (ci >= aQ) return;
-    const int64_t slot = cr_slot[Q * T + ci];
-    if (slot < 0 || slot >= Q * T) return;
-    const int64_t R = slot / T;
-    const int64_t c = cr_c[Q * T + ci];
-    const int64_t o = (int64_t)((uint32_t)U_idx[slot] & ~BLEND_BIT);
-    if (o < 0 || o >= n || c < 0 || c >= n) return;
-    V u = unite(Pay<V>::ld(U_suf, slot), Pay<V>::ld(cr_pre, Q * T + ci));
-    u = unite(u, range_union<V>(ptot, upre, usuf, sp, nb, R + 1, Q - 1));
-    sink.emit(o, u);
-    sink.emit(c, u);
+                                             const void *__restrict__ sp,
+                                             const void *__restrict__ spb, int64_t M, int64_t nb,
+                                             SINK sink) {
+    // one thread per close record; records are dense, their count is on the
+    // device.  Four records per step, so their dependent loads overlap.
+    constexpr int U = 4;
+    const int64_t total = *crtot;
+    const int64_t stride = (int64_t)gridDim.x * W;
+    for (int64_t r0 = (int64_t)blockIdx.x * W + threadIdx.x; r0 < total; r0 += U * stride) {
+        int64_t slot[U], c[U], o[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t r = r0 + q * stride;
+            slot[q] = r < total ? cr_slot[r] : -1;
+            c[q] = r < total ? cr_c[r] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            o[q] = -1;
+            if (slot[q] < 0 || c[q] < 0 || c[q] >= n || slot[q] / T >= c[q] / T) continue;
+            o[q] = (int64_t)((uint32_t)U_idx[slot[q]] & ~BLEND_BIT);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (o[q] < 0 || o[q] >= n) continue;
+            const int64_t r = r0 + q * stride;
+            const int64_t Q = c[q] / T, R = slot[q] / T;
+            V u = unite(Pay<V>::ld(U_suf, slot[q]), Pay<V>::ld(cr_pre, r));
+            u = unite(u, range_union<V>(upre, usuf, sp, spb, M, nb, R + 1, Q - 1));
+            sink.emit(o[q], u);
+            sink.emit(c[q], u);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ sinks
@@ -937,7 +1003,9 @@ FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad) {
     L.pinfo = take(sizeof(int4) * M);
     L.part = take(sizeof(int4) * M);
     L.mtree = take(sizeof(int) * 2 * Mp);
-    L.bagg = take(sizeof(int2) * ((Mp + SB - 1) / SB + 1));
+    L.bagg = take(sizeof(int4) * ((Mp + SB - 1) / SB + 1));
+    L.crbase = take(sizeof(int) * M);
+    L.crtot = take(sizeof(int) * 4);
     L.jptr0 = take(sizeof(int32_t) * M);
     L.jptr1 = take(sizeof(int32_t) * M);
     L.jval0 = take(vbytes * M);
@@ -954,6 +1022,7 @@ FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad) {
     L.upre = take(vbytes * M);
     L.usuf = take(vbytes * M);
     L.sp = take(vbytes * nb * lv);
+    L.spb = take(vbytes * M * UBL);
     L.status = take(sizeof(uint32_t) * (S > 0 ? S : 1));
     if (grad) {
         L.acc = take(sizeof(unsigned long long) * 4 * (n > 0 ? n : 1));
@@ -972,16 +1041,18 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     int4 *pinfo = (int4 *)(w + L.pinfo);
     int4 *part = (int4 *)(w + L.part);
     int *mtree = (int *)(w + L.mtree);
+    int *crbase = (int *)(w + L.crbase);
+    int *crtot = (int *)(w + L.crtot);
     int32_t *U_idx = (int32_t *)(w + L.U_idx);
     void *U_cum = w + L.U_cum;
-    k_reduce<BOXES, V><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
+    k_reduce<BOXES, V><<<(unsigned)((M + RW - 1) / RW), RW * WAVE, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
     {
-        int2 *bagg = (int2 *)(w + L.bagg);
+        int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
         k_spine_blocks<<<(unsigned)nbk, SB, 0, st>>>(pinfo, M, bagg);
-        k_spine_top<<<1, SB, 0, st>>>(bagg, nbk, off, S, n, status);
+        k_spine_top<<<1, SB, 0, st>>>(bagg, nbk, off, S, n, status, crtot);
         const int64_t nbt = (L.Mp + SB - 1) / SB;
-        k_spine_apply<<<(unsigned)nbt, SB, 0, st>>>(pinfo, M, bagg, part, mtree, L.Mp);
+        k_spine_apply<<<(unsigned)nbt, SB, 0, st>>>(pinfo, M, bagg, part, mtree, L.Mp, crbase);
         if (L.Mp > SB) k_spine_treetop<<<1, SB, 0, st>>>(mtree, L.Mp);
     }
     int32_t *jp[2] = {(int32_t *)(w + L.jptr0), (int32_t *)(w + L.jptr1)};
@@ -1009,17 +1080,19 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     if (prof) (void)hipEventRecord(g_prof_before, st);
     k_resolve<BOXES, V, SINK><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs,
                                                          rhead, jv[cur], U_idx, U_cum, U_suf,
-                                                         cr_slot, cr_c, cr_pre, ptot, match, pm,
-                                                         sink, status);
+                                                         crbase, cr_slot, cr_c, cr_pre, ptot, match,
+                                                         pm, sink, status);
     if (prof) (void)hipEventRecord(g_prof_after, st);
     if (BOXES) {
         void *upre = w + L.upre;
         void *usuf = w + L.usuf;
         void *sp = w + L.sp;
-        k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp);
+        void *spb = w + L.spb;
+        k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp, spb);
         k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
-        k_cross<V, SINK><<<(unsigned)(M * (T / W)), W, 0, st>>>(pinfo, M, n, U_idx, U_suf, cr_slot, cr_c,
-                                                     cr_pre, ptot, upre, usuf, sp, L.nb, sink);
+        const int64_t gx = min((int64_t)(n + W - 1) / W, (int64_t)256 * 32);
+        k_cross<V, SINK><<<(unsigned)gx, W, 0, st>>>(crtot, n, U_idx, U_suf, cr_slot, cr_c, cr_pre,
+                                                      upre, usuf, sp, spb, M, L.nb, sink);
     }
     return hipGetLastError();
 }
