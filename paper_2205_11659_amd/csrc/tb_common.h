@@ -121,24 +121,45 @@ struct Pay<BoxS> {
 };
 
 // ---------------------------------------------------------- wave shuffles
-__device__ __forceinline__ int shfl_up(int v, int d) { return __shfl_up(v, d, WAVE); }
-__device__ __forceinline__ float shfl_up(float v, int d) { return __shfl_up(v, d, WAVE); }
-__device__ __forceinline__ Box shfl_up(Box v, int d) {
-    return {shfl_up(v.x0, d), shfl_up(v.y0, d), shfl_up(v.x1, d), shfl_up(v.y1, d)};
+// DPP lane moves (GFX9 data-parallel primitives): the source lane is read
+// through the VALU crossbar, with no LDS round trip.  Lanes whose source lies
+// outside the pattern, or outside `RM` (a mask of 16-lane rows), keep `old`.
+namespace dpp {
+constexpr int SHR1 = 0x111, SHR2 = 0x112, SHR4 = 0x114, SHR8 = 0x118;  // lane i <- i-k, in row
+constexpr int SHL1 = 0x101, SHL2 = 0x102, SHL4 = 0x104, SHL8 = 0x108;  // lane i <- i+k, in row
+constexpr int WSHR1 = 0x138, WSHL1 = 0x130;                            // lane i <- i-1 / i+1
+constexpr int BC15 = 0x142, BC31 = 0x143;  // row r <- lane 16r-1 / lane 31
+}  // namespace dpp
+template <int C, int RM = 0xF>
+__device__ __forceinline__ int dmov(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, C, RM, 0xF, false);
 }
-__device__ __forceinline__ BoxS shfl_up(BoxS v, int d) {
-    return {shfl_up(v.x0, d), shfl_up(v.y0, d), shfl_up(v.x1, d), shfl_up(v.y1, d),
-            shfl_up((int)v.s0, d), shfl_up((int)v.s1, d), shfl_up((int)v.s2, d), shfl_up((int)v.s3, d)};
+template <int C, int RM = 0xF>
+__device__ __forceinline__ float dmov(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), C, RM, 0xF, false));
 }
-__device__ __forceinline__ int shfl_xor(int v, int m) { return __shfl_xor(v, m, WAVE); }
-__device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, WAVE); }
-__device__ __forceinline__ Box shfl_xor(Box v, int m) {
-    return {shfl_xor(v.x0, m), shfl_xor(v.y0, m), shfl_xor(v.x1, m), shfl_xor(v.y1, m)};
+template <int C, int RM = 0xF>
+__device__ __forceinline__ Box dmov(Box o, Box v) {
+    return {dmov<C, RM>(o.x0, v.x0), dmov<C, RM>(o.y0, v.y0), dmov<C, RM>(o.x1, v.x1), dmov<C, RM>(o.y1, v.y1)};
 }
-__device__ __forceinline__ BoxS shfl_xor(BoxS v, int m) {
-    return {shfl_xor(v.x0, m), shfl_xor(v.y0, m), shfl_xor(v.x1, m), shfl_xor(v.y1, m),
-            shfl_xor((int)v.s0, m), shfl_xor((int)v.s1, m), shfl_xor((int)v.s2, m), shfl_xor((int)v.s3, m)};
+template <int C, int RM = 0xF>
+__device__ __forceinline__ BoxS dmov(BoxS o, BoxS v) {
+    return {dmov<C, RM>(o.x0, v.x0), dmov<C, RM>(o.y0, v.y0), dmov<C, RM>(o.x1, v.x1), dmov<C, RM>(o.y1, v.y1),
+            dmov<C, RM>(o.s0, v.s0), dmov<C, RM>(o.s1, v.s1), dmov<C, RM>(o.s2, v.s2), dmov<C, RM>(o.s3, v.s3)};
 }
+// uniform read of one lane
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ Box rdlane(Box v, int l) {
+    return {rdlane(v.x0, l), rdlane(v.y0, l), rdlane(v.x1, l), rdlane(v.y1, l)};
+}
+__device__ __forceinline__ BoxS rdlane(BoxS v, int l) {
+    return {rdlane(v.x0, l), rdlane(v.y0, l), rdlane(v.x1, l), rdlane(v.y1, l),
+            rdlane(v.s0, l), rdlane(v.s1, l), rdlane(v.s2, l), rdlane(v.s3, l)};
+}
+
 // arbitrary-lane reads
 __device__ __forceinline__ Box shfl_idx(Box v, int src) {
     return {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE), __shfl(v.y1, src, WAVE)};
@@ -154,9 +175,25 @@ __device__ __forceinline__ BoxS shfl_idx(BoxS v, int src) {
 struct Seg {
     int r, v;
 };
-__device__ __forceinline__ Seg shfl_up(Seg s, int d) { return {shfl_up(s.r, d), shfl_up(s.v, d)}; }
+template <int C, int RM = 0xF>
+__device__ __forceinline__ Seg dmov(Seg o, Seg v) { return {dmov<C, RM>(o.r, v.r), dmov<C, RM>(o.v, v.v)}; }
+__device__ __forceinline__ Seg rdlane(Seg v, int l) { return {rdlane(v.r, l), rdlane(v.v, l)}; }
 struct SegOp {
     __device__ Seg operator()(Seg x, Seg y) const { return y.r ? y : Seg{x.r, x.v + y.v}; }
+};
+// A segmented sum carried together with a plain sum u.
+struct SegU {
+    int r, v, u;
+};
+template <int C, int RM = 0xF>
+__device__ __forceinline__ SegU dmov(SegU o, SegU v) {
+    return {dmov<C, RM>(o.r, v.r), dmov<C, RM>(o.v, v.v), dmov<C, RM>(o.u, v.u)};
+}
+__device__ __forceinline__ SegU rdlane(SegU v, int l) { return {rdlane(v.r, l), rdlane(v.v, l), rdlane(v.u, l)}; }
+struct SegUOp {
+    __device__ SegU operator()(SegU x, SegU y) const {
+        return y.r ? SegU{1, y.v, x.u + y.u} : SegU{x.r, x.v + y.v, x.u + y.u};
+    }
 };
 // Bicyclic element with scene resets: (a pops of the stack below, b
 // unmatched opens left, r a reset occurred).  (a,b) ⊕ (c,d) is the paper's
@@ -165,19 +202,17 @@ struct SegOp {
 struct BicR {
     int a, b, r;
 };
-__device__ __forceinline__ BicR shfl_up(BicR x, int d) {
-    return {shfl_up(x.a, d), shfl_up(x.b, d), shfl_up(x.r, d)};
+template <int C, int RM = 0xF>
+__device__ __forceinline__ BicR dmov(BicR o, BicR v) {
+    return {dmov<C, RM>(o.a, v.a), dmov<C, RM>(o.b, v.b), dmov<C, RM>(o.r, v.r)};
 }
+__device__ __forceinline__ BicR rdlane(BicR v, int l) { return {rdlane(v.a, l), rdlane(v.b, l), rdlane(v.r, l)}; }
 __device__ __forceinline__ BicR bicr(const BicR &x, const BicR &y) {
     const int m = x.b < y.a ? x.b : y.a;
     return {x.a + (x.r ? 0 : y.a - m), y.r ? y.b : x.b + y.b - m, x.r | y.r};
 }
 struct BicROp {
     __device__ BicR operator()(BicR x, BicR y) const { return bicr(x, y); }
-};
-// the same product with its operands swapped, for scans run right to left
-struct BicRRevOp {
-    __device__ BicR operator()(BicR x, BicR y) const { return bicr(y, x); }
 };
 struct MinOp {
     __device__ int operator()(int a, int b) const { return a < b ? a : b; }
@@ -199,26 +234,44 @@ __device__ __forceinline__ BicR shfl_idx(BicR x, int src) {
 }
 __device__ __forceinline__ int shfl_idx(int x, int src) { return __shfl(x, src, WAVE); }
 
+// Inclusive scan inside one wave for an associative `op` with identity `id`
+// (operands in lane order): in-row steps of 1, 2, 4, 8 lanes, then the row
+// totals are carried across rows 0->1, 2->3 and 1->2,3.
 template <class V, class Op>
-__device__ __forceinline__ V wave_incl_scan(V v, Op op) {
-    const int lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        V u = shfl_up(v, o);
-        if (lane >= o) v = op(u, v);
-    }
+__device__ __forceinline__ V wave_incl_scan(V v, Op op, V id) {
+    v = op(dmov<dpp::SHR1>(id, v), v);
+    v = op(dmov<dpp::SHR2>(id, v), v);
+    v = op(dmov<dpp::SHR4>(id, v), v);
+    v = op(dmov<dpp::SHR8>(id, v), v);
+    v = op(dmov<dpp::BC15, 0xA>(id, v), v);
+    v = op(dmov<dpp::BC31, 0xC>(id, v), v);
     return v;
 }
 
 // Exclusive scan inside one wave; also returns the wave total.
 template <class V, class Op>
 __device__ __forceinline__ V wave_excl_scan(V v, Op op, V ident, V *total) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const V inc = wave_incl_scan(v, op);
-    *total = shfl_idx(inc, WAVE - 1);
-    V ex = shfl_up(inc, 1);
-    if (lane == 0) ex = ident;
-    return ex;
+    const V inc = wave_incl_scan(v, op, ident);
+    *total = rdlane(inc, WAVE - 1);
+    return dmov<dpp::WSHR1>(ident, inc);
+}
+
+// Exclusive suffix scan inside one wave: lane l gets op over lanes l+1..63
+// in lane order (identity at lane 63); also returns the wave total.
+template <class V, class Op>
+__device__ __forceinline__ V wave_excl_suffix_scan(V v, Op op, V id, V *total) {
+    v = op(v, dmov<dpp::SHL1>(id, v));
+    v = op(v, dmov<dpp::SHL2>(id, v));
+    v = op(v, dmov<dpp::SHL4>(id, v));
+    v = op(v, dmov<dpp::SHL8>(id, v));
+    // lanes 16r hold row r's suffix; carry the later rows' product in
+    const V t1 = rdlane(v, 16), t2 = rdlane(v, 32), t3 = rdlane(v, 48);
+    const V r1 = op(t2, t3), r0 = op(t1, r1);
+    const int row = (threadIdx.x & (WAVE - 1)) >> 4;
+    const V later = row == 0 ? r0 : row == 1 ? r1 : row == 2 ? t3 : id;
+    v = op(v, later);
+    *total = rdlane(v, 0);
+    return dmov<dpp::WSHL1>(id, v);
 }
 
 // Exclusive scan over the NW*64 threads of a workgroup; `sh` holds NW values.
@@ -226,7 +279,7 @@ __device__ __forceinline__ V wave_excl_scan(V v, Op op, V ident, V *total) {
 template <int NW, class V, class Op>
 __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *total) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    V inc = wave_incl_scan(v, op);
+    V inc = wave_incl_scan(v, op, ident);
     if (lane == WAVE - 1) sh[wid] = inc;
     __syncthreads();
     V pre = ident, tot = ident;
@@ -235,8 +288,7 @@ __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *tota
         if (w < wid) pre = op(pre, sh[w]);
         tot = op(tot, sh[w]);
     }
-    V ex = shfl_up(inc, 1);
-    if (lane == 0) ex = ident;
+    const V ex = dmov<dpp::WSHR1>(ident, inc);
     *total = tot;
     __syncthreads();
     return op(pre, ex);
@@ -371,32 +423,45 @@ __device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[KK], uint32_t rm
 __device__ __forceinline__ void mintree_build(int *mt, int v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
     mt[W + t] = v;
-#pragma unroll
-    for (int l = 1; (1 << l) <= WAVE; ++l) {
-        const int o = shfl_xor(v, 1 << (l - 1));
-        v = o < v ? o : v;
-        if ((lane & ((1 << l) - 1)) == 0) mt[(W + t) >> l] = v;
-    }
+    // after step l, a lane whose low l bits are all set holds the min of its
+    // aligned group of 2^l lanes (out-of-pattern lanes combine with themselves)
+    v = min(v, dmov<dpp::SHR1>(v, v));
+    if ((lane & 1) == 1) mt[(W + t) >> 1] = v;
+    v = min(v, dmov<dpp::SHR2>(v, v));
+    if ((lane & 3) == 3) mt[(W + t) >> 2] = v;
+    v = min(v, dmov<dpp::SHR4>(v, v));
+    if ((lane & 7) == 7) mt[(W + t) >> 3] = v;
+    v = min(v, dmov<dpp::SHR8>(v, v));
+    if ((lane & 15) == 15) mt[(W + t) >> 4] = v;
+    v = min(v, dmov<dpp::BC15, 0xA>(v, v));
+    if ((lane & 31) == 31) mt[(W + t) >> 5] = v;
+    v = min(v, dmov<dpp::BC31, 0xC>(v, v));
+    if (lane == 63) mt[(W + t) >> 6] = v;
     __syncthreads();
     if (t == 0)
         for (int x = NWAVE - 1; x >= 1; --x) mt[x] = min(mt[2 * x], mt[2 * x + 1]);
     __syncthreads();
 }
 
-// The same for a union tree of boxes.
+// The wave levels of a union tree of boxes over the W threads: leaves at
+// W + t, internal nodes down to one node per wave (indices NWAVE..2*NWAVE-1).
+// No barrier; nodes above the wave level are not built.
 template <class V>
-__device__ __forceinline__ void uniontree_build(V *ut, V v) {
+__device__ __forceinline__ void uniontree_wave(V *ut, V v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
     ut[W + t] = v;
-#pragma unroll
-    for (int l = 1; (1 << l) <= WAVE; ++l) {
-        v = unite(v, shfl_xor(v, 1 << (l - 1)));
-        if ((lane & ((1 << l) - 1)) == 0) ut[(W + t) >> l] = v;
-    }
-    __syncthreads();
-    if (t == 0)
-        for (int x = NWAVE - 1; x >= 1; --x) ut[x] = unite(ut[2 * x], ut[2 * x + 1]);
-    __syncthreads();
+    v = unite(v, dmov<dpp::SHR1>(v, v));
+    if ((lane & 1) == 1) ut[(W + t) >> 1] = v;
+    v = unite(v, dmov<dpp::SHR2>(v, v));
+    if ((lane & 3) == 3) ut[(W + t) >> 2] = v;
+    v = unite(v, dmov<dpp::SHR4>(v, v));
+    if ((lane & 7) == 7) ut[(W + t) >> 3] = v;
+    v = unite(v, dmov<dpp::SHR8>(v, v));
+    if ((lane & 15) == 15) ut[(W + t) >> 4] = v;
+    v = unite(v, dmov<dpp::BC15, 0xA>(v, v));
+    if ((lane & 31) == 31) ut[(W + t) >> 5] = v;
+    v = unite(v, dmov<dpp::BC31, 0xC>(v, v));
+    if (lane == 63) ut[(W + t) >> 6] = v;
 }
 
 // rightmost leaf s < t with leaf value < v, or -1
@@ -426,16 +491,24 @@ __device__ __forceinline__ int mintree_range_min(const int *mt, int lo, int hi) 
     return r;
 }
 
-// union over leaves [lo, hi] of an LDS segment tree of boxes (EMPTY if empty)
+// Union over leaves [lo, hi] of a tree built by uniontree_wave, for
+// 1 <= lo and hi <= W-2 (EMPTY if lo > hi).  Such a range never covers a
+// node above the wave level, so seven levels suffice.  Straight-line: every
+// LDS read is issued before the first is used (unused reads fetch leaf 0).
 template <class V>
-__device__ __forceinline__ V uniontree_range(const V *ut, int lo, int hi) {
+__device__ __forceinline__ V uniontree_inner(const V *ut, int lo, int hi) {
     V r = Pay<V>::empty();
-    if (lo > hi) return r;
     int l = lo + W, h = hi + W + 1;
-    while (l < h) {
-        if (l & 1) r = unite(r, ut[l++]);
-        if (h & 1) r = unite(r, ut[--h]);
-        l >>= 1, h >>= 1;
+#pragma unroll
+    for (int lev = 0; lev < 7; ++lev) {
+        const bool go = l < h;
+        const bool ul = go && (l & 1), uh = go && (h & 1);
+        const V a = ut[ul ? l : W];
+        const V b = ut[uh ? h - 1 : W];
+        if (ul) r = unite(r, a);
+        if (uh) r = unite(r, b);
+        l = (l + (ul ? 1 : 0)) >> 1;
+        h = (h - (uh ? 1 : 0)) >> 1;
     }
     return r;
 }

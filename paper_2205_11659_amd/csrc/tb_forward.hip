@@ -85,12 +85,9 @@ __global__ __launch_bounds__(RW * WAVE) void k_reduce(const uint32_t *__restrict
     const int D = pre.r ? pre.b : pre.b - pre.a;  // partition-relative unless a reset came first
     const int base = wk.rs ? 0 : D - wk.a;
     const int baseP = tot.r ? 0 : -tot.a;
-    // suffix (later lanes): how many of this lane's unmatched opens they pop.
-    // Lane l scans lane 63-l's value with the swapped product, then hands the
-    // result back.
+    // suffix (later lanes): how many of this lane's unmatched opens they pop
     BicR rt;
-    const BicR rsuf = wave_excl_scan(shfl_idx(mine, WAVE - 1 - lane), BicRRevOp{}, BicR{0, 0, 0}, &rt);
-    const BicR suf = shfl_idx(rsuf, WAVE - 1 - lane);
+    const BicR suf = wave_excl_suffix_scan(mine, BicROp{}, BicR{0, 0, 0}, &rt);
     const int b = mine.b;
     const int ns = suf.r ? 0 : (b > suf.a ? b - suf.a : 0);
 
@@ -368,7 +365,7 @@ __device__ __forceinline__ int find_run(const int4 *runs, int nruns, int64_t L) 
 // Slot of the entry at level L >= 1 held by an earlier partition (global U
 // slot), or -1.  Continues the owner walk when the stored runs end early.
 __device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 head,
-                                 const int4 *__restrict__ part, int64_t *owner) {
+                                 const int4 *__restrict__ part, int64_t M, int64_t *owner) {
     int64_t R = -1, base = 0;
     const int r = find_run(runs, nruns, L);
     if (r >= 0) {
@@ -376,7 +373,7 @@ __device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 he
         base = runs[r].w;
     } else if (!head.w) {
         int64_t RR = head.y, hi = head.z;
-        while (RR >= 0 && hi >= L) {
+        while (RR >= 0 && RR < M && hi >= L) {
             const int4 pr = part[RR];
             if (L > pr.z && L <= hi) {
                 R = RR;
@@ -389,28 +386,42 @@ __device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 he
         }
     }
     *owner = R;
-    if (R < 0 || L - base - 1 < 0 || L - base - 1 >= T) return -1;
+    if (R < 0 || R >= M || L - base - 1 < 0 || L - base - 1 >= T) return -1;
     return R * T + (L - base - 1);
 }
 
 template <bool BOXES, class V>
 struct ResolveSmem {
     int4 runs[RMAX];
-    // incoming levels [preM, dP], entry x = level preM + x: the open's index
-    // (| BLEND_BIT) or -1 for the root, and its clip context.  After the walk
-    // the context array is reused as the union tree over threads.
-    int inc_idx[T + 1];
-    V inc_ctx[BOXES ? T + 1 : 1];
-    V ucum[BOXES ? T : 1];  // local clip prefix of thread U entries; later suffix unions
-    V jval[BOXES ? W : 1];  // clip context at each thread's base level
+    // Until the walk ends: the clip context at each thread's base level, and
+    // the incoming levels [preM, dP] (entry x = level preM + x: the open's
+    // index | BLEND_BIT, or -1 for the root).  Afterwards: the union tree
+    // over threads.
+    union Early {
+        struct {
+            V jval[BOXES ? W : 1];
+            int inc_idx[T + 1];
+        } w;
+        V ut[BOXES ? 2 * W : 1];
+    } e;
+    // Clip contexts.  Entries [0, aP] belong to the incoming levels; from
+    // aP + 1 on come the unmatched opens of each thread in order (thread t's
+    // from aP + 1 + tub[t]) with their local clip prefix, which the union
+    // phase replaces by suffix unions.  A partition's incoming pops (aP) and
+    // its threads' unmatched opens are different elements, so T + 1 entries
+    // always suffice.
+    V cx[BOXES ? T + 1 : 1];
     uint8_t tkind[T];
     int tcm[W];
     int tbase[W];
+    int tub[W];  // unmatched opens of the threads before this one
     uint8_t tum[W];
     int mt[2 * W];
     int tlink[W];  // owner thread of each thread's base level (prev smaller cm), or -1
     int jptr[W];
-    Seg sh_seg[NWAVE];
+    SegU sh_seg[NWAVE];
+    V wtot[NWAVE];  // union of each wave's leaves
+    int wmin[NWAVE];  // lowest level each wave reaches
 };
 
 template <bool BOXES, class V, class SINK>
@@ -425,9 +436,10 @@ __global__ __launch_bounds__(W) void k_resolve(
     int32_t *__restrict__ match, int32_t *__restrict__ pm, SINK sink,
     uint32_t *__restrict__ status) {
     __shared__ ResolveSmem<BOXES, V> sm;
-    V *ut = sm.inc_ctx;  // valid once the walk is over
+    V *ut = sm.e.ut;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
     const int64_t P = blockIdx.x;
+    const int64_t M = gridDim.x;
     const int64_t p0 = P * T;
     const int64_t g0 = p0 + (int64_t)t * K;
     const int4 myp = part[P];
@@ -464,7 +476,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         const int64_t L = preM + x;
         if (x > aP || L < 1) continue;
         int64_t R;
-        const int64_t slot = incoming_slot(L, sm.runs, nruns, head, part, &R);
+        const int64_t slot = incoming_slot(L, sm.runs, nruns, head, part, M, &R);
         if (slot < 0) continue;
         g_idx[q] = U_idx[slot];
         if (BOXES) g_ctx[q] = isect(Pay<V>::ld(U_cum, slot), Pay<V>::ld(base_ctx, R));
@@ -473,25 +485,29 @@ __global__ __launch_bounds__(W) void k_resolve(
     // ---- per-thread walk and thread-level depths
     const Walk wk = walk_kinds<K>(ks, rm);
     const int b = __popc(wk.umask);
-    Seg segtot;
-    const Seg ex = block_excl_scan<NWAVE>(Seg{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a}, SegOp{},
-                                          Seg{0, 0}, sm.sh_seg, &segtot);
+    SegU segtot;
+    const SegU ex = block_excl_scan<NWAVE>(SegU{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a, b}, SegUOp{},
+                                           SegU{0, 0, 0}, sm.sh_seg, &segtot);
+    const int ub = aP + 1 + ex.u;  // this thread's first entry in cx
     const int64_t Dt = ex.r ? (int64_t)ex.v : dP + ex.v;  // absolute depth at thread start
     const int64_t pre_m = Dt - wk.a;
     const int cm = wk.rs ? SENT : (int)pre_m;
     const int base = wk.rs ? 0 : (int)pre_m;
     sm.tcm[t] = cm;
     sm.tbase[t] = base;
+    sm.tub[t] = ub;
     sm.tum[t] = (uint8_t)wk.umask;
 #pragma unroll
     for (int j = 0; j < K; ++j) sm.tkind[t * K + j] = (uint8_t)ks[j];
     if (BOXES) {
         V c = Pay<V>::inf();
+        int e = ub;
 #pragma unroll
         for (int p = 0; p < K; ++p) {
             if ((wk.umask >> p) & 1u) {
                 if (ks[p] == BCLIP) c = isect(c, bx[p]);
-                sm.ucum[t * K + p] = c;
+                if (e <= T) sm.cx[e] = c;
+                ++e;
             }
         }
     }
@@ -499,8 +515,8 @@ __global__ __launch_bounds__(W) void k_resolve(
     for (int q = 0; q < NG; ++q) {
         const int x = t + q * W;
         if (x > aP) continue;
-        sm.inc_idx[x] = g_idx[q];
-        if (BOXES) sm.inc_ctx[x] = g_ctx[q];
+        sm.e.w.inc_idx[x] = g_idx[q];
+        if (BOXES) sm.cx[x] = g_ctx[q];
     }
     mintree_build(sm.mt, cm);  // its barriers also publish everything above
 
@@ -522,13 +538,13 @@ __global__ __launch_bounds__(W) void k_resolve(
             if (s >= 0) {
                 const int64_t jj = pre_m - sm.tbase[s] - 1;
                 const uint32_t um = sm.tum[s];
-                if (jj >= 0 && jj < __popc(um)) {
-                    v = sm.ucum[s * K + nth_bit(um, (int)jj)];
+                if (jj >= 0 && jj < __popc(um) && sm.tub[s] + jj <= T) {
+                    v = sm.cx[sm.tub[s] + jj];
                     ptr = s;
                 }
             } else {
                 const int64_t x = pre_m - preM;
-                if (x >= 0 && x <= aP) v = sm.inc_ctx[x];
+                if (x >= 0 && x <= aP) v = sm.cx[x];
             }
         }
 #pragma unroll
@@ -542,15 +558,15 @@ __global__ __launch_bounds__(W) void k_resolve(
                 ptr = pp;
             }
         }
-        sm.jval[t] = v;
+        sm.e.w.jval[t] = v;
         sm.jptr[t] = ptr;
         for (int r = 0; r < NWAVE && __syncthreads_or(ptr >= 0); ++r) {  // also publishes tlink
             if (ptr >= 0) {
-                v = isect(v, sm.jval[ptr]);
+                v = isect(v, sm.e.w.jval[ptr]);
                 ptr = sm.jptr[ptr];
             }
             __syncthreads();
-            sm.jval[t] = v;
+            sm.e.w.jval[t] = v;
             sm.jptr[t] = ptr;
         }
         __syncthreads();
@@ -558,43 +574,48 @@ __global__ __launch_bounds__(W) void k_resolve(
         __syncthreads();  // publishes tlink
     }
 
-    // ---- sequential walk over this thread's elements with a register stack
-    // of local opens (index 0 = top; pushes and pops shift), each entry with
-    // its clip context and the union of leaves seen since it was opened.
+    // ---- this thread's elements in order.  The thread's own opens form a
+    // stack held as a bit mask of positions (top = highest bit), each with
+    // the clip context inside it; levels below come from lookups.  Rows are
+    // collected in registers and written once at the end.
     int64_t sid = off ? scene_of(off, S, g0) : 0;
     int64_t soff = off ? off[sid] : 0;
-    uint32_t defmask = 0;
-    int depth = 0;  // local stack depth
+    uint32_t mask = 0;    // open positions on the local stack
+    uint32_t clipm = 0;   // positions holding BEGIN_CLIP
+    uint32_t leafm = 0;   // positions holding leaves (the only rows unions read)
+    uint32_t keep = 0;    // rows this thread writes at the end
+    uint32_t mkeep = 0;   // match rows this thread writes at the end
+    uint32_t lbm = 0;     // closes of blends opened in this thread
+    uint32_t defmask = 0; // closes of blends opened before this thread
     bool rseen = false;
     int64_t dep = Dt;
-    int st_pos[K], st_kind[K];
-    V st_ctx[K], st_acc[K], lout[K];
-    int def_own[K], def_pos[K];
+    V octx[K], res[K];
+    int mv[K], lbp[K], def_own[K], def_pos[K], def_ent[K];
     int64_t def_L[K];
     // the stack entry at level `cur_L` seen from this thread's start; the
     // levels asked for only decrease, so the owner search moves left along
     // owner links from the previous thread
     int64_t cur_L = INT64_MIN, cur_idx = -1;
     int own_s = t - 1;
-    int cur_kind = -1, cur_own = -1, cur_pos = -1;
+    int cur_kind = -1, cur_own = -1, cur_pos = -1, cur_ent = -1;
     V cur_ctx = Pay<V>::inf();
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        st_pos[j] = 0;
-        st_kind[j] = 0;
-        st_ctx[j] = Pay<V>::inf();
-        st_acc[j] = Pay<V>::empty();
-        lout[j] = Pay<V>::empty();
-        def_own[j] = def_pos[j] = -1;
+        octx[j] = Pay<V>::inf();
+        res[j] = Pay<V>::empty();
+        mv[j] = -1;
+        lbp[j] = 0;
+        def_own[j] = def_pos[j] = def_ent[j] = -1;
         def_L[j] = 0;
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < K; ++j) {
         const int64_t i = g0 + j;
         const bool real = i < n;
+        const uint32_t bit = 1u << j;
         if ((rm >> j) & 1u) {
             if (real && i > 0 && dep != 0) flag(status, off, S, i - 1, ST_UNBAL);
-            depth = 0;
+            mask = 0;
             rseen = true;
             dep = 0;
             if (off && real) {
@@ -603,7 +624,8 @@ __global__ __launch_bounds__(W) void k_resolve(
             }
         }
         if (real && kr[j] > 4u) flag(status, off, S, i, ST_BAD_KIND);
-        if (depth == 0 && !rseen && cur_L != dep) {
+        const int tp = mask ? msb32(mask) : -1;
+        if (tp < 0 && !rseen && cur_L != dep) {
             cur_L = dep;
             cur_idx = -1;
             cur_kind = -1;
@@ -612,11 +634,11 @@ __global__ __launch_bounds__(W) void k_resolve(
             if (dep >= 1 && dep <= lowtop) {
                 const int64_t x = dep - preM;
                 if (x >= 0 && x <= aP) {
-                    const int u = sm.inc_idx[x];
+                    const int u = sm.e.w.inc_idx[x];
                     if (u != -1) {
                         cur_idx = (int64_t)((uint32_t)u & ~BLEND_BIT);
                         cur_kind = ((uint32_t)u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
-                        if (BOXES) cur_ctx = sm.inc_ctx[x];
+                        if (BOXES) cur_ctx = sm.cx[x];
                     }
                 }
             } else if (dep > lowtop) {
@@ -625,85 +647,65 @@ __global__ __launch_bounds__(W) void k_resolve(
                 if (s >= 0) {
                     const int64_t jj = dep - sm.tbase[s] - 1;
                     const uint32_t um = sm.tum[s];
-                    if (jj >= 0 && jj < __popc(um)) {
+                    const int e = sm.tub[s] + (int)jj;
+                    if (jj >= 0 && jj < __popc(um) && e <= T) {
                         const int p = nth_bit(um, (int)jj);
                         cur_idx = p0 + (int64_t)s * K + p;
-                        if (BOXES) cur_ctx = isect(sm.jval[s], sm.ucum[s * K + p]);
+                        if (BOXES) cur_ctx = isect(sm.e.w.jval[s], sm.cx[e]);
                         cur_kind = sm.tkind[s * K + p];
                         cur_own = s;
                         cur_pos = p;
+                        cur_ent = e;
                     }
                 }
             }
         }
-        int64_t top;
-        V ctx;
-        if (depth > 0) {
-            top = g0 + st_pos[0];
-            ctx = st_ctx[0];
-        } else if (rseen) {
-            top = -1;
-            ctx = Pay<V>::inf();
-        } else {
-            top = cur_idx;
-            ctx = cur_ctx;
+        // the top of the stack before this element: a local open, the scene
+        // root after a reset, or the looked-up entry
+        int64_t top = rseen ? -1 : cur_idx;
+        V ctx = rseen ? Pay<V>::inf() : cur_ctx;
+#pragma unroll
+        for (int q = 0; q < j; ++q) {
+            if (q == tp) {
+                top = g0 + q;
+                if (BOXES) ctx = octx[q];
+            }
         }
         if (pm && real) pm[i] = top >= 0 ? (int32_t)(top - soff) : -1;
         const uint32_t k = ks[j];
         if (k == LEAF) {
-            if (BOXES) {
-                const V o = canon(isect(bx[j], ctx));
-                lout[j] = o;
-                st_acc[0] = unite(st_acc[0], o);  // harmless when the stack is empty
-                if (real) sink.emit(i, o);
-            }
-            if (match && real) match[i] = -1;
+            if (BOXES) res[j] = canon(isect(bx[j], ctx));
+            leafm |= bit;
+            keep |= bit;
+            mkeep |= bit;
         } else if (is_open(k)) {
-            V c = ctx;
+            if (BOXES) {
+                octx[j] = k == BCLIP ? isect(bx[j], ctx) : ctx;
+                if (k == BCLIP) res[j] = canon(octx[j]);
+            }
             if (k == BCLIP) {
-                c = isect(bx[j], ctx);
-                if (BOXES && real) sink.emit(i, canon(c));
+                clipm |= bit;
+                keep |= bit;
             }
-#pragma unroll
-            for (int q = K - 1; q > 0; --q) {
-                st_pos[q] = st_pos[q - 1];
-                st_kind[q] = st_kind[q - 1];
-                st_ctx[q] = st_ctx[q - 1];
-                st_acc[q] = st_acc[q - 1];
-            }
-            st_pos[0] = j;
-            st_kind[0] = (int)k;
-            st_ctx[0] = c;
-            st_acc[0] = Pay<V>::empty();
-            ++depth;
+            mask |= bit;
             ++dep;
-        } else if (depth > 0) {  // close matched inside this thread
-            const int p = st_pos[0];
-            const int ko = st_kind[0];
-            const V oc = st_ctx[0];
-            const V acc = st_acc[0];
-#pragma unroll
-            for (int q = 0; q < K - 1; ++q) {
-                st_pos[q] = st_pos[q + 1];
-                st_kind[q] = st_kind[q + 1];
-                st_ctx[q] = st_ctx[q + 1];
-                st_acc[q] = st_acc[q + 1];
-            }
-            st_acc[0] = unite(st_acc[0], acc);  // leaves flow up to the new top
-            --depth;
+        } else if (tp >= 0) {  // close of an open of this thread
+            const int p = tp;
+            mask &= ~(1u << p);
             --dep;
-            if ((k == ECLIP) != (ko == (int)BCLIP) && real) flag(status, off, S, i, ST_MISMATCH);
-            if (match && real) {
-                match[i] = (int32_t)(g0 + p - soff);
-                match[g0 + p] = (int32_t)(i - soff);
-            }
-            if (BOXES && real) {
-                if (k == ECLIP) {
-                    sink.emit(i, canon(oc));
-                } else {
-                    sink.emit(i, acc);
-                    sink.emit(g0 + p, acc);
-                }
+            if ((k == ECLIP) != (((clipm >> p) & 1u) != 0) && real) flag(status, off, S, i, ST_MISMATCH);
+            mv[j] = (int32_t)(g0 + p - soff);
+#pragma unroll
+            for (int q = 0; q < j; ++q)
+                if (q == p) mv[q] = (int32_t)(i - soff);
+            mkeep |= bit | (1u << p);
+            if (k == ECLIP) {
+                if (BOXES) res[j] = canon(ctx);
+                keep |= bit;
+            } else {
+                lbm |= bit;
+                lbp[j] = p;
+                keep |= bit | (1u << p);
             }
         } else if (rseen) {  // close below its scene's root
             if (real) flag(status, off, S, i, ST_UNBAL);
@@ -714,29 +716,28 @@ __global__ __launch_bounds__(W) void k_resolve(
             } else {
                 if (((k == ECLIP) != (cur_kind == (int)BCLIP)) && real)
                     flag(status, off, S, i, ST_MISMATCH);
-                if (match && real) {
-                    match[i] = (int32_t)(cur_idx - soff);
-                    if (cur_idx < n) match[cur_idx] = (int32_t)(i - soff);
-                }
-                if (BOXES && real) {
-                    if (k == ECLIP) {
-                        sink.emit(i, canon(cur_ctx));
-                    } else {
-                        defmask |= 1u << j;
-                        def_L[j] = L;
-                        def_own[j] = cur_own;
-                        def_pos[j] = cur_pos;
-                    }
+                mv[j] = (int32_t)(cur_idx - soff);
+                mkeep |= bit;
+                if (match && real && cur_idx < n) match[cur_idx] = (int32_t)(i - soff);
+                if (k == ECLIP) {
+                    if (BOXES) res[j] = canon(ctx);
+                    keep |= bit;
+                } else if (BOXES && real) {
+                    defmask |= bit;
+                    def_L[j] = L;
+                    def_own[j] = cur_own;
+                    def_pos[j] = cur_pos;
+                    def_ent[j] = cur_ent;
                 }
             }
             // every pop of a partition-incoming level leaves a record
             if (BOXES && cur_own < 0) {
                 const int64_t ci = dP - L;
-                if (ci >= 0 && ci < aP) {
+                if (ci >= 0 && ci < aP && (uint64_t)(rbase + ci) < (uint64_t)n) {
                     int32_t sl = -1;
                     if (k == EBLEND && real && L >= 1 && cur_idx >= 0) {
                         int64_t R;
-                        sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, &R);
+                        sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, M, &R);
                     }
                     cr_slot[rbase + ci] = sl;
                     cr_c[rbase + ci] = (int32_t)i;
@@ -745,58 +746,114 @@ __global__ __launch_bounds__(W) void k_resolve(
             --dep;
         }
     }
+    // blends opened and closed in this thread: the union of the leaves between
+    if (BOXES) {
+#pragma unroll
+        for (int j = 1; j < K; ++j) {
+            if (!((lbm >> j) & 1u)) continue;
+            const int p = lbp[j];
+            V u = Pay<V>::empty();
+#pragma unroll
+            for (int q = 1; q < j; ++q)
+                if (q > p && ((leafm >> q) & 1u)) u = unite(u, res[q]);
+            res[j] = u;
+#pragma unroll
+            for (int q = 0; q < j; ++q)
+                if (q == p) res[q] = u;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (((keep >> j) & 1u) && g0 + j < n) sink.emit(g0 + j, res[j]);
+    }
+    if (match) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (((mkeep >> j) & 1u) && g0 + j < n) match[g0 + j] = mv[j];
+    }
     if (!BOXES) return;
 
-    // ---- unions that cross threads or partitions
+    // ---- unions that cross threads or partitions.  Prefix and suffix
+    // unions over threads come from wave scans plus the wave totals; only
+    // blends opened and closed in different threads of this partition need
+    // an arbitrary range, answered from a union tree over threads.
     V ttot = Pay<V>::empty();
 #pragma unroll
-    for (int j = 0; j < K; ++j) ttot = unite(ttot, lout[j]);
-    __syncthreads();  // the walk's reads of inc_ctx / jval / ucum are done
-    uniontree_build(ut, ttot);
+    for (int j = 0; j < K; ++j)
+        if ((leafm >> j) & 1u) ttot = unite(ttot, res[j]);
+    const int wid = t >> 6;
+    V wtot_u;
+    const V wpre = wave_excl_scan(ttot, UniteOp{}, Pay<V>::empty(), &wtot_u);
+    V wsuf_dummy;
+    const V wsuf = wave_excl_suffix_scan(ttot, UniteOp{}, Pay<V>::empty(), &wsuf_dummy);
+    int wmin;
+    const int wsufmin = wave_excl_suffix_scan(cm, MinOp{}, INT32_MAX, &wmin);
+    __syncthreads();  // the walk's reads of the early tables and cx are done
+    uniontree_wave(ut, ttot);
+    if (lane == 0) {
+        sm.wtot[wid] = wtot_u;
+        sm.wmin[wid] = wmin;
+    }
     {  // suffix unions after each of this thread's unmatched opens
         V suf = Pay<V>::empty();
+        int e = ub + __popc(wk.umask);
 #pragma unroll
         for (int p = K - 1; p >= 0; --p) {
-            if ((wk.umask >> p) & 1u) sm.ucum[t * K + p] = suf;
-            suf = unite(suf, lout[p]);
+            if ((wk.umask >> p) & 1u) {
+                --e;
+                if (e <= T) sm.cx[e] = suf;
+            }
+            if ((leafm >> p) & 1u) suf = unite(suf, res[p]);
         }
     }
     __syncthreads();
+    V pre_t = wpre, suf_t = wsuf, all = Pay<V>::empty();
+    int sufmin = wsufmin;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) {
+        const V x = sm.wtot[w];
+        if (w < wid) pre_t = unite(pre_t, x);
+        if (w > wid) {
+            suf_t = unite(suf_t, x);
+            sufmin = min(sufmin, sm.wmin[w]);
+        }
+        all = unite(all, x);
+    }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!((defmask >> j) & 1u)) continue;
         V pre = Pay<V>::empty();
 #pragma unroll
-        for (int q = 0; q < K; ++q)
-            if (q < j) pre = unite(pre, lout[q]);
+        for (int q = 0; q < j; ++q)
+            if ((leafm >> q) & 1u) pre = unite(pre, res[q]);
         const int64_t i = g0 + j;
         if (def_own[j] >= 0) {
             const int s = def_own[j];
-            const V u = unite(unite(sm.ucum[s * K + def_pos[j]], uniontree_range(ut, s + 1, t - 1)), pre);
+            const V u = unite(unite(sm.cx[def_ent[j]], uniontree_inner(ut, s + 1, t - 1)), pre);
             sink.emit(i, u);
             sink.emit(p0 + (int64_t)s * K + def_pos[j], u);
         } else {
             const int64_t ci = dP - def_L[j];
-            if (ci >= 0 && ci < aP) Pay<V>::st(cr_pre, rbase + ci, unite(uniontree_range(ut, 0, t - 1), pre));
+            if (ci >= 0 && ci < aP && (uint64_t)(rbase + ci) < (uint64_t)n)
+                Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
         }
     }
     // surviving blend opens: union from the open to the end of the partition
     {
-        const int sufmin = mintree_range_min(sm.mt, t + 1, W - 1);
         const int64_t baseP = (int64_t)myp.z;
         int jj = 0;
 #pragma unroll
         for (int p = 0; p < K; ++p) {
             if (!((wk.umask >> p) & 1u)) continue;
             const int64_t L = (int64_t)base + 1 + jj;
+            const int e = ub + jj;
             ++jj;
             if (L > (int64_t)sufmin || ks[p] != BBLEND) continue;
             const int64_t slot = L - baseP - 1;
-            if (slot < 0 || slot >= T) continue;
-            Pay<V>::st(U_suf, p0 + slot, unite(sm.ucum[t * K + p], uniontree_range(ut, t + 1, W - 1)));
+            if (slot < 0 || slot >= T || e > T) continue;
+            Pay<V>::st(U_suf, p0 + slot, unite(sm.cx[e], suf_t));
         }
     }
-    if (t == 0) Pay<V>::st(ptot, P, ut[1]);
+    if (t == 0) Pay<V>::st(ptot, P, all);
 }
 
 // ------------------------------------------------ range unions over partitions
@@ -888,7 +945,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
     // one thread per close record; records are dense, their count is on the
     // device.  Four records per step, so their dependent loads overlap.
     constexpr int U = 4;
-    const int64_t total = *crtot;
+    const int64_t total = min((int64_t)*crtot, n);  // at most one record per element
     const int64_t stride = (int64_t)gridDim.x * W;
     for (int64_t r0 = (int64_t)blockIdx.x * W + threadIdx.x; r0 < total; r0 += U * stride) {
         int64_t slot[U], c[U], o[U];
