@@ -518,11 +518,16 @@ __global__ __launch_bounds__(W) void k_resolve(
         sm.e.w.inc_idx[x] = g_idx[q];
         if (BOXES) sm.cx[x] = g_ctx[q];
     }
+    int wmin0;
+    int premin = wave_excl_scan(cm, MinOp{}, INT32_MAX, &wmin0);  // lowest level of earlier lanes
     mintree_build(sm.mt, cm);  // its barriers also publish everything above
 
     // levels at or below `lowtop` are held by no earlier thread of this
     // partition: they come from earlier partitions (the LDS table).
-    const int64_t lowtop = min((int64_t)mintree_range_min(sm.mt, 0, t - 1), Dt);
+#pragma unroll
+    for (int w = 0; w < NWAVE - 1; ++w)
+        if (w < (t >> 6)) premin = min(premin, sm.mt[NWAVE + w]);  // wave nodes of the min tree
+    const int64_t lowtop = min((int64_t)premin, Dt);
     // owner links between threads: the entry just below a thread's lowest
     // level belongs to the nearest earlier thread with a smaller lowest level
     const int tl = wk.rs ? -1 : mintree_prev_less(sm.mt, t, cm);
@@ -818,24 +823,43 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
         all = unite(all, x);
     }
+    // closes of blends opened in an earlier partition: the prefix part
+    uint32_t dloc = 0;  // closes of blends opened in an earlier thread of this partition
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!((defmask >> j) & 1u)) continue;
+        if (def_own[j] >= 0) {
+            dloc |= 1u << j;
+            continue;
+        }
         V pre = Pay<V>::empty();
 #pragma unroll
         for (int q = 0; q < j; ++q)
             if ((leafm >> q) & 1u) pre = unite(pre, res[q]);
-        const int64_t i = g0 + j;
-        if (def_own[j] >= 0) {
-            const int s = def_own[j];
-            const V u = unite(unite(sm.cx[def_ent[j]], uniontree_inner(ut, s + 1, t - 1)), pre);
-            sink.emit(i, u);
-            sink.emit(p0 + (int64_t)s * K + def_pos[j], u);
-        } else {
-            const int64_t ci = dP - def_L[j];
-            if (ci >= 0 && ci < aP && (uint64_t)(rbase + ci) < (uint64_t)n)
-                Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
+        const int64_t ci = dP - def_L[j];
+        if (ci >= 0 && ci < aP && (uint64_t)(rbase + ci) < (uint64_t)n)
+            Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
+    }
+    // closes of blends opened in an earlier thread of this partition, taken
+    // one per round so a wave runs as many rounds as its busiest lane needs
+    for (int it = 0; it < K && __ballot(dloc != 0); ++it) {
+        if (!dloc) continue;
+        const int j = __builtin_ctz(dloc);
+        dloc &= dloc - 1;
+        int s = 0, ent = 0, pos = 0;
+        V pre = Pay<V>::empty();
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (q == j) {
+                s = def_own[q];
+                ent = def_ent[q];
+                pos = def_pos[q];
+            }
+            if (q < j && ((leafm >> q) & 1u)) pre = unite(pre, res[q]);
         }
+        const V u = unite(unite(sm.cx[ent], uniontree_inner(ut, s + 1, t - 1)), pre);
+        sink.emit(g0 + j, u);
+        sink.emit(p0 + (int64_t)s * K + pos, u);
     }
     // surviving blend opens: union from the open to the end of the partition
     {
@@ -943,15 +967,16 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
                                              const void *__restrict__ spb, int64_t M, int64_t nb,
                                              SINK sink) {
     // one thread per close record; records are dense, their count is on the
-    // device.  Four records per step, so their dependent loads overlap.
+    // device.  A workgroup takes contiguous chunks of U*W records (few pages
+    // per wave), four records per thread so their dependent loads overlap.
     constexpr int U = 4;
     const int64_t total = min((int64_t)*crtot, n);  // at most one record per element
-    const int64_t stride = (int64_t)gridDim.x * W;
-    for (int64_t r0 = (int64_t)blockIdx.x * W + threadIdx.x; r0 < total; r0 += U * stride) {
+    for (int64_t c0 = (int64_t)blockIdx.x * (U * W); c0 < total; c0 += (int64_t)gridDim.x * (U * W)) {
+        const int64_t r0 = c0 + threadIdx.x;
         int64_t slot[U], c[U], o[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int64_t r = r0 + q * stride;
+            const int64_t r = r0 + q * W;
             slot[q] = r < total ? cr_slot[r] : -1;
             c[q] = r < total ? cr_c[r] : -1;
         }
@@ -964,7 +989,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             if (o[q] < 0 || o[q] >= n) continue;
-            const int64_t r = r0 + q * stride;
+            const int64_t r = r0 + q * W;
             const int64_t Q = c[q] / T, R = slot[q] / T;
             V u = unite(Pay<V>::ld(U_suf, slot[q]), Pay<V>::ld(cr_pre, r));
             u = unite(u, range_union<V>(upre, usuf, sp, spb, M, nb, R + 1, Q - 1));
