@@ -21,6 +21,33 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALG_BYTES_FWD = 40  # kind 4 + box 16 in; match 4 + box 16 out
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_resolve_scene128M_traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources the measured kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2205_11659_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel
+    calibration), or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
 
 
 class HipEvents:
@@ -192,7 +219,8 @@ def main():
         "path_hbm_frac": round(ALG_BYTES_FWD * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": "k_resolve", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "kernel_ms": round(k_ms, 4), "traffic": None},
+                     "kernel_ms": round(k_ms, 4), "traffic": measured_traffic(),
+                     "alg_bytes": ALG_BYTES_FWD * n},
     }
     if not args.no_extra:
         del kind, box, out, match
