@@ -444,11 +444,12 @@ __device__ __forceinline__ void mintree_build(int *mt, int v) {
 }
 
 // The wave levels of a union tree of boxes over the W threads: leaves at
-// W + t, internal nodes down to one node per wave (indices NWAVE..2*NWAVE-1).
-// No barrier; nodes above the wave level are not built.
+// W + t, internal nodes down to one node per wave (indices NWAVE..2*NWAVE-1),
+// and EMPTY at index 0.  No barrier; nodes above the wave level are not built.
 template <class V>
 __device__ __forceinline__ void uniontree_wave(V *ut, V v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
+    if (t == 0) ut[0] = Pay<V>::empty();  // the "no node" sentinel of uniontree_inner
     ut[W + t] = v;
     v = unite(v, dmov<dpp::SHR1>(v, v));
     if ((lane & 1) == 1) ut[(W + t) >> 1] = v;
@@ -494,7 +495,8 @@ __device__ __forceinline__ int mintree_range_min(const int *mt, int lo, int hi) 
 // Union over leaves [lo, hi] of a tree built by uniontree_wave, for
 // 1 <= lo and hi <= W-2 (EMPTY if lo > hi).  Such a range never covers a
 // node above the wave level, so seven levels suffice.  Straight-line: every
-// LDS read is issued before the first is used (unused reads fetch leaf 0).
+// LDS read is issued before the first is used; a level that contributes
+// nothing reads node 0, which uniontree_wave sets to EMPTY.
 template <class V>
 __device__ __forceinline__ V uniontree_inner(const V *ut, int lo, int hi) {
     V r = Pay<V>::empty();
@@ -503,10 +505,8 @@ __device__ __forceinline__ V uniontree_inner(const V *ut, int lo, int hi) {
     for (int lev = 0; lev < 7; ++lev) {
         const bool go = l < h;
         const bool ul = go && (l & 1), uh = go && (h & 1);
-        const V a = ut[ul ? l : W];
-        const V b = ut[uh ? h - 1 : W];
-        if (ul) r = unite(r, a);
-        if (uh) r = unite(r, b);
+        r = unite(r, ut[ul ? l : 0]);
+        r = unite(r, ut[uh ? h - 1 : 0]);
         l = (l + (ul ? 1 : 0)) >> 1;
         h = (h - (uh ? 1 : 0)) >> 1;
     }

@@ -411,13 +411,12 @@ struct ResolveSmem {
     // its threads' unmatched opens are different elements, so T + 1 entries
     // always suffice.
     V cx[BOXES ? T + 1 : 1];
-    uint8_t tkind[T];
-    int tcm[W];
-    int tbase[W];
-    int tub[W];  // unmatched opens of the threads before this one
-    uint8_t tum[W];
+    // per thread: {lowest level (SENT after a scene start), owner thread or
+    // -1, base level, first cx entry | unmatched-open mask << 16 | mask of
+    // those that are clips << 20}; one LDS read per owner-chain hop
+    int4 tinfo[W];
+    static_assert(K <= 4 && T < 0xFFFF, "tinfo packs 4-bit masks and 16-bit entries");
     int mt[2 * W];
-    int tlink[W];  // owner thread of each thread's base level (prev smaller cm), or -1
     int jptr[W];
     SegU sh_seg[NWAVE];
     V wtot[NWAVE];  // union of each wave's leaves
@@ -438,17 +437,20 @@ __global__ __launch_bounds__(W) void k_resolve(
     __shared__ ResolveSmem<BOXES, V> sm;
     V *ut = sm.e.ut;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
-    const int64_t P = blockIdx.x;
-    const int64_t M = gridDim.x;
-    const int64_t p0 = P * T;
-    const int64_t g0 = p0 + (int64_t)t * K;
+    // Element indices and levels fit in 32 bits (n < 2^31); element indices
+    // are unsigned so that a last partition past 2^31 - T cannot overflow.
+    const uint32_t P = blockIdx.x;
+    const uint32_t M = gridDim.x;
+    const uint32_t p0 = P * T;
+    const uint32_t g0 = p0 + (uint32_t)t * K;
+    const uint32_t un = (uint32_t)n;
     const int4 myp = part[P];
-    const int64_t dP = myp.x;
+    const int dP = myp.x;
     const int aP = pinfo[P].x;
-    const int64_t preM = dP - aP;  // lowest incoming level any element here can see
+    const int preM = dP - aP;  // lowest incoming level any element here can see
     const int4 head = rhead_g[P];
     const int nruns = head.x;
-    const int64_t rbase = crbase[P];  // this partition's close records start here
+    const int rbase = crbase[P];  // this partition's close records start here
 
     // ---- loads: inputs, owner runs
     uint32_t kr[K], ks[K];
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         g_idx[q] = -1;
         g_ctx[q] = Pay<V>::inf();
         const int x = t + q * W;
-        const int64_t L = preM + x;
+        const int L = preM + x;
         if (x > aP || L < 1) continue;
         int64_t R;
         const int64_t slot = incoming_slot(L, sm.runs, nruns, head, part, M, &R);
@@ -489,16 +491,17 @@ __global__ __launch_bounds__(W) void k_resolve(
     const SegU ex = block_excl_scan<NWAVE>(SegU{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a, b}, SegUOp{},
                                            SegU{0, 0, 0}, sm.sh_seg, &segtot);
     const int ub = aP + 1 + ex.u;  // this thread's first entry in cx
-    const int64_t Dt = ex.r ? (int64_t)ex.v : dP + ex.v;  // absolute depth at thread start
-    const int64_t pre_m = Dt - wk.a;
+    const int Dt = ex.r ? ex.v : dP + ex.v;  // absolute depth at thread start
+    const int pre_m = Dt - wk.a;
     const int cm = wk.rs ? SENT : (int)pre_m;
     const int base = wk.rs ? 0 : (int)pre_m;
-    sm.tcm[t] = cm;
-    sm.tbase[t] = base;
-    sm.tub[t] = ub;
-    sm.tum[t] = (uint8_t)wk.umask;
+    {
+        uint32_t clipm = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) sm.tkind[t * K + j] = (uint8_t)ks[j];
+        for (int j = 0; j < K; ++j)
+            if (ks[j] == BCLIP) clipm |= 1u << j;
+        sm.tinfo[t] = make_int4(cm, -1, base, (int)((uint32_t)ub | (wk.umask << 16) | ((clipm & wk.umask) << 20)));
+    }
     if (BOXES) {
         V c = Pay<V>::inf();
         int e = ub;
@@ -527,11 +530,11 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
     for (int w = 0; w < NWAVE - 1; ++w)
         if (w < (t >> 6)) premin = min(premin, sm.mt[NWAVE + w]);  // wave nodes of the min tree
-    const int64_t lowtop = min((int64_t)premin, Dt);
+    const int lowtop = min(premin, Dt);
     // owner links between threads: the entry just below a thread's lowest
     // level belongs to the nearest earlier thread with a smaller lowest level
     const int tl = wk.rs ? -1 : mintree_prev_less(sm.mt, t, cm);
-    sm.tlink[t] = tl;
+    sm.tinfo[t].y = tl;
 
     // ---- clip context at each thread's base level: pointer jumping along
     // owner threads, first inside the wave with shuffles, then across waves.
@@ -541,19 +544,20 @@ __global__ __launch_bounds__(W) void k_resolve(
         if (!wk.rs && pre_m > 0) {
             const int s = tl;
             if (s >= 0) {
-                const int64_t jj = pre_m - sm.tbase[s] - 1;
-                const uint32_t um = sm.tum[s];
-                if (jj >= 0 && jj < __popc(um) && sm.tub[s] + jj <= T) {
-                    v = sm.cx[sm.tub[s] + jj];
+                const int4 ti = sm.tinfo[s];
+                const int jj = pre_m - ti.z - 1;
+                const uint32_t um = ((uint32_t)ti.w >> 16) & 0xFu;
+                const int e = (ti.w & 0xFFFF) + (int)jj;
+                if (jj >= 0 && jj < __popc(um) && e <= T) {
+                    v = sm.cx[e];
                     ptr = s;
                 }
             } else {
-                const int64_t x = pre_m - preM;
+                const int x = pre_m - preM;
                 if (x >= 0 && x <= aP) v = sm.cx[x];
             }
         }
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
+        for (int r = 0; r < 6 && __ballot(ptr >= wbase); ++r) {  // until no lane points inside the wave
             const bool in = ptr >= wbase;
             const int src = in ? ptr - wbase : lane;
             const V vv = shfl_idx(v, src);
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     // the clip context inside it; levels below come from lookups.  Rows are
     // collected in registers and written once at the end.
     int64_t sid = off ? scene_of(off, S, g0) : 0;
-    int64_t soff = off ? off[sid] : 0;
+    int soff = off ? (int)off[sid] : 0;
     uint32_t mask = 0;    // open positions on the local stack
     uint32_t clipm = 0;   // positions holding BEGIN_CLIP
     uint32_t leafm = 0;   // positions holding leaves (the only rows unions read)
@@ -592,15 +596,16 @@ __global__ __launch_bounds__(W) void k_resolve(
     uint32_t mkeep = 0;   // match rows this thread writes at the end
     uint32_t lbm = 0;     // closes of blends opened in this thread
     uint32_t defmask = 0; // closes of blends opened before this thread
+    uint32_t errs = 0;    // status bits, 4 per element; element g0 - 1 at bit 4K
     bool rseen = false;
-    int64_t dep = Dt;
+    int dep = Dt;
     V octx[K], res[K];
     int mv[K], lbp[K], def_own[K], def_pos[K], def_ent[K];
-    int64_t def_L[K];
+    int def_L[K];
     // the stack entry at level `cur_L` seen from this thread's start; the
     // levels asked for only decrease, so the owner search moves left along
     // owner links from the previous thread
-    int64_t cur_L = INT64_MIN, cur_idx = -1;
+    int cur_L = INT32_MIN, cur_idx = -1;
     int own_s = t - 1;
     int cur_kind = -1, cur_own = -1, cur_pos = -1, cur_ent = -1;
     V cur_ctx = Pay<V>::inf();
@@ -615,20 +620,20 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < K; ++j) {
-        const int64_t i = g0 + j;
-        const bool real = i < n;
+        const uint32_t i = g0 + j;
+        const bool real = i < un;
         const uint32_t bit = 1u << j;
         if ((rm >> j) & 1u) {
-            if (real && i > 0 && dep != 0) flag(status, off, S, i - 1, ST_UNBAL);
+            if (real && i > 0 && dep != 0) errs |= ST_UNBAL << (j > 0 ? 4 * (j - 1) : 4 * K);  // element i - 1
             mask = 0;
             rseen = true;
             dep = 0;
             if (off && real) {
                 sid = scene_of(off, S, i);
-                soff = off[sid];
+                soff = (int)off[sid];
             }
         }
-        if (real && kr[j] > 4u) flag(status, off, S, i, ST_BAD_KIND);
+        if (real && kr[j] > 4u) errs |= ST_BAD_KIND << (4 * j);
         const int tp = mask ? msb32(mask) : -1;
         if (tp < 0 && !rseen && cur_L != dep) {
             cur_L = dep;
@@ -637,27 +642,31 @@ __global__ __launch_bounds__(W) void k_resolve(
             cur_own = -1;
             cur_ctx = Pay<V>::inf();
             if (dep >= 1 && dep <= lowtop) {
-                const int64_t x = dep - preM;
+                const int x = dep - preM;
                 if (x >= 0 && x <= aP) {
                     const int u = sm.e.w.inc_idx[x];
                     if (u != -1) {
-                        cur_idx = (int64_t)((uint32_t)u & ~BLEND_BIT);
+                        cur_idx = (int)((uint32_t)u & ~BLEND_BIT);
                         cur_kind = ((uint32_t)u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
                         if (BOXES) cur_ctx = sm.cx[x];
                     }
                 }
             } else if (dep > lowtop) {
-                while (own_s >= 0 && (int64_t)sm.tcm[own_s] >= dep) own_s = sm.tlink[own_s];
+                int4 ti = sm.tinfo[own_s >= 0 ? own_s : 0];
+                while (own_s >= 0 && ti.x >= dep) {
+                    own_s = ti.y;
+                    if (own_s >= 0) ti = sm.tinfo[own_s];
+                }
                 const int s = own_s;
                 if (s >= 0) {
-                    const int64_t jj = dep - sm.tbase[s] - 1;
-                    const uint32_t um = sm.tum[s];
-                    const int e = sm.tub[s] + (int)jj;
+                    const int jj = dep - ti.z - 1;
+                    const uint32_t um = ((uint32_t)ti.w >> 16) & 0xFu;
+                    const int e = (ti.w & 0xFFFF) + (int)jj;
                     if (jj >= 0 && jj < __popc(um) && e <= T) {
                         const int p = nth_bit(um, (int)jj);
-                        cur_idx = p0 + (int64_t)s * K + p;
+                        cur_idx = (int)(p0 + (uint32_t)s * K + p);
                         if (BOXES) cur_ctx = isect(sm.e.w.jval[s], sm.cx[e]);
-                        cur_kind = sm.tkind[s * K + p];
+                        cur_kind = (((uint32_t)ti.w >> (20 + p)) & 1u) ? (int)BCLIP : (int)BBLEND;
                         cur_own = s;
                         cur_pos = p;
                         cur_ent = e;
@@ -667,88 +676,81 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
         // the top of the stack before this element: a local open, the scene
         // root after a reset, or the looked-up entry
-        int64_t top = rseen ? -1 : cur_idx;
+        int top = rseen ? -1 : cur_idx;
         V ctx = rseen ? Pay<V>::inf() : cur_ctx;
 #pragma unroll
         for (int q = 0; q < j; ++q) {
             if (q == tp) {
-                top = g0 + q;
+                top = (int)(g0 + q);
                 if (BOXES) ctx = octx[q];
             }
         }
         if (pm && real) pm[i] = top >= 0 ? (int32_t)(top - soff) : -1;
+        // every case below is computed with selects: the wave runs one
+        // straight-line step per element however its lanes' kinds differ
         const uint32_t k = ks[j];
-        if (k == LEAF) {
-            if (BOXES) res[j] = canon(isect(bx[j], ctx));
-            leafm |= bit;
-            keep |= bit;
-            mkeep |= bit;
-        } else if (is_open(k)) {
-            if (BOXES) {
-                octx[j] = k == BCLIP ? isect(bx[j], ctx) : ctx;
-                if (k == BCLIP) res[j] = canon(octx[j]);
-            }
-            if (k == BCLIP) {
-                clipm |= bit;
-                keep |= bit;
-            }
-            mask |= bit;
-            ++dep;
-        } else if (tp >= 0) {  // close of an open of this thread
-            const int p = tp;
-            mask &= ~(1u << p);
-            --dep;
-            if ((k == ECLIP) != (((clipm >> p) & 1u) != 0) && real) flag(status, off, S, i, ST_MISMATCH);
-            mv[j] = (int32_t)(g0 + p - soff);
+        const bool isleaf = k == LEAF;
+        const bool isopen = is_open(k);
+        const bool isclose = !isleaf && !isopen;
+        const bool lclose = isclose && tp >= 0;            // closes an open of this thread
+        const bool rootclose = isclose && tp < 0 && rseen;  // closes below its scene's root
+        const bool rclose = isclose && tp < 0 && !rseen;    // closes a level held before this thread
+        const bool rok = rclose && dep > 0 && cur_idx >= 0;
+        const int tps = tp < 0 ? 0 : tp;
+        const uint32_t pbit = lclose ? (1u << tps) : 0u;
+        if (BOXES) {
+            const V ix = isect(bx[j], ctx);
+            octx[j] = k == BCLIP ? ix : ctx;
+            // leaf: its clipped box; BEGIN_CLIP: likewise; END_CLIP: the
+            // context inside its open.  Blend rows are filled in later.
+            res[j] = canon(isleaf || k == BCLIP ? ix : ctx);
+        }
+        const bool mism = (lclose && ((k == ECLIP) != (((clipm >> tps) & 1u) != 0))) ||
+                          (rok && ((k == ECLIP) != (cur_kind == (int)BCLIP)));
+        errs |= (real && mism) ? ST_MISMATCH << (4 * j) : 0u;
+        errs |= (real && (rootclose || (rclose && !rok))) ? ST_UNBAL << (4 * j) : 0u;
+        leafm |= isleaf ? bit : 0u;
+        clipm |= k == BCLIP ? bit : 0u;
+        keep |= (isleaf || k == BCLIP || (k == ECLIP && (lclose || rok))) ? bit : 0u;
+        keep |= (lclose && k == EBLEND) ? (bit | pbit) : 0u;
+        lbm |= (lclose && k == EBLEND) ? bit : 0u;
+        lbp[j] = tps;
+        mkeep |= (isleaf || lclose || rok) ? bit : 0u;
+        mkeep |= pbit;
+        mv[j] = lclose ? (int32_t)(g0 + tps - soff) : rok ? (int32_t)(cur_idx - soff) : -1;
 #pragma unroll
-            for (int q = 0; q < j; ++q)
-                if (q == p) mv[q] = (int32_t)(i - soff);
-            mkeep |= bit | (1u << p);
-            if (k == ECLIP) {
-                if (BOXES) res[j] = canon(ctx);
-                keep |= bit;
-            } else {
-                lbm |= bit;
-                lbp[j] = p;
-                keep |= bit | (1u << p);
-            }
-        } else if (rseen) {  // close below its scene's root
-            if (real) flag(status, off, S, i, ST_UNBAL);
-        } else {  // close of the open at level `dep`, held before this thread
-            const int64_t L = dep;
-            if (L <= 0 || cur_idx < 0) {
-                if (real) flag(status, off, S, i, ST_UNBAL);
-            } else {
-                if (((k == ECLIP) != (cur_kind == (int)BCLIP)) && real)
-                    flag(status, off, S, i, ST_MISMATCH);
-                mv[j] = (int32_t)(cur_idx - soff);
-                mkeep |= bit;
-                if (match && real && cur_idx < n) match[cur_idx] = (int32_t)(i - soff);
-                if (k == ECLIP) {
-                    if (BOXES) res[j] = canon(ctx);
-                    keep |= bit;
-                } else if (BOXES && real) {
-                    defmask |= bit;
-                    def_L[j] = L;
-                    def_own[j] = cur_own;
-                    def_pos[j] = cur_pos;
-                    def_ent[j] = cur_ent;
+        for (int q = 0; q < j; ++q)
+            if (lclose && q == tp) mv[q] = (int32_t)(i - soff);
+        if (rok && match && real && (uint32_t)cur_idx < un) match[cur_idx] = (int32_t)(i - soff);
+        if (BOXES && rok && k == EBLEND && real) {
+            defmask |= bit;
+            def_L[j] = dep;
+            def_own[j] = cur_own;
+            def_pos[j] = cur_pos;
+            def_ent[j] = cur_ent;
+        }
+        // every pop of a partition-incoming level leaves a record
+        if (BOXES && rclose && cur_own < 0) {
+            const int L = dep;
+            const int ci = dP - L;
+            if (ci >= 0 && ci < aP && (uint32_t)(rbase + ci) < un) {
+                int32_t sl = -1;
+                if (k == EBLEND && real && L >= 1 && cur_idx >= 0) {
+                    int64_t R;
+                    sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, M, &R);
                 }
+                cr_slot[rbase + ci] = sl;
+                cr_c[rbase + ci] = (int32_t)i;
             }
-            // every pop of a partition-incoming level leaves a record
-            if (BOXES && cur_own < 0) {
-                const int64_t ci = dP - L;
-                if (ci >= 0 && ci < aP && (uint64_t)(rbase + ci) < (uint64_t)n) {
-                    int32_t sl = -1;
-                    if (k == EBLEND && real && L >= 1 && cur_idx >= 0) {
-                        int64_t R;
-                        sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, M, &R);
-                    }
-                    cr_slot[rbase + ci] = sl;
-                    cr_c[rbase + ci] = (int32_t)i;
-                }
-            }
-            --dep;
+        }
+        mask = isopen ? (mask | bit) : (mask & ~pbit);
+        dep += isopen ? 1 : (lclose || rclose) ? -1 : 0;
+    }
+    if (errs) {  // malformed input only: raise each element's bits in its scene's word
+#pragma unroll
+        for (int j = 0; j <= K; ++j) {
+            const uint32_t bj = (errs >> (4 * j)) & 0xFu;
+            if (bj) flag(status, off, S, j < K ? (int64_t)g0 + j : (int64_t)g0 - 1, bj);
         }
     }
     // blends opened and closed in this thread: the union of the leaves between
@@ -768,12 +770,12 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (((keep >> j) & 1u) && g0 + j < n) sink.emit(g0 + j, res[j]);
+            if (((keep >> j) & 1u) && g0 + j < un) sink.emit(g0 + j, res[j]);
     }
     if (match) {
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (((mkeep >> j) & 1u) && g0 + j < n) match[g0 + j] = mv[j];
+            if (((mkeep >> j) & 1u) && g0 + j < un) match[g0 + j] = mv[j];
     }
     if (!BOXES) return;
 
@@ -836,8 +838,8 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
         for (int q = 0; q < j; ++q)
             if ((leafm >> q) & 1u) pre = unite(pre, res[q]);
-        const int64_t ci = dP - def_L[j];
-        if (ci >= 0 && ci < aP && (uint64_t)(rbase + ci) < (uint64_t)n)
+        const int ci = dP - def_L[j];
+        if (ci >= 0 && ci < aP && (uint32_t)(rbase + ci) < un)
             Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
     }
     // closes of blends opened in an earlier thread of this partition, taken
@@ -859,22 +861,22 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
         const V u = unite(unite(sm.cx[ent], uniontree_inner(ut, s + 1, t - 1)), pre);
         sink.emit(g0 + j, u);
-        sink.emit(p0 + (int64_t)s * K + pos, u);
+        sink.emit(p0 + (uint32_t)s * K + pos, u);
     }
     // surviving blend opens: union from the open to the end of the partition
     {
-        const int64_t baseP = (int64_t)myp.z;
+        const int baseP = myp.z;
         int jj = 0;
 #pragma unroll
         for (int p = 0; p < K; ++p) {
             if (!((wk.umask >> p) & 1u)) continue;
-            const int64_t L = (int64_t)base + 1 + jj;
+            const int L = base + 1 + jj;
             const int e = ub + jj;
             ++jj;
-            if (L > (int64_t)sufmin || ks[p] != BBLEND) continue;
-            const int64_t slot = L - baseP - 1;
+            if (L > sufmin || ks[p] != BBLEND) continue;
+            const int slot = L - baseP - 1;
             if (slot < 0 || slot >= T || e > T) continue;
-            Pay<V>::st(U_suf, p0 + slot, unite(sm.cx[e], suf_t));
+            Pay<V>::st(U_suf, p0 + (uint32_t)slot, unite(sm.cx[e], suf_t));
         }
     }
     if (t == 0) Pay<V>::st(ptot, P, all);
@@ -931,29 +933,6 @@ __global__ __launch_bounds__(1024) void k_usparse(void *__restrict__ sp, int64_t
     }
 }
 
-// union of partition totals over partitions [a, b]: O(1) loads
-template <class V>
-__device__ V range_union(const void *upre, const void *usuf, const void *sp, const void *spb,
-                         int64_t M, int64_t nb, int64_t a, int64_t b) {
-    V u = Pay<V>::empty();
-    if (a > b) return u;
-    const int64_t ba = a / UB, bb = b / UB;
-    if (ba == bb) {
-        // levels stop at 2^(UBL-1): two spans of that length cover a whole block
-        const int lv = min(63 - __clzll((unsigned long long)(b - a + 1)), UBL - 1);
-        u = unite(Pay<V>::ld(spb, lv * M + a), Pay<V>::ld(spb, lv * M + b - ((int64_t)1 << lv) + 1));
-        return u;
-    }
-    u = unite(Pay<V>::ld(usuf, a), Pay<V>::ld(upre, b));
-    const int64_t l0 = ba + 1, l1 = bb - 1;
-    if (l0 <= l1) {
-        const int lv = 63 - __clzll((unsigned long long)(l1 - l0 + 1));
-        u = unite(u, Pay<V>::ld(sp, lv * nb + l0));
-        u = unite(u, Pay<V>::ld(sp, lv * nb + l1 - ((int64_t)1 << lv) + 1));
-    }
-    return u;
-}
-
 template <class V, class SINK>
 __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int64_t n,
                                              const int32_t *__restrict__ U_idx,
@@ -968,33 +947,60 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
                                              SINK sink) {
     // one thread per close record; records are dense, their count is on the
     // device.  A workgroup takes contiguous chunks of U*W records (few pages
-    // per wave), four records per thread so their dependent loads overlap.
-    constexpr int U = 4;
+    // per wave), U records per thread.  After the records themselves, every
+    // load of a record is issued at once: invalid lanes read entry 0 and
+    // discard it, so no load waits behind a branch.
+    constexpr int U = sizeof(V) <= 16 ? 4 : 2;
     const int64_t total = min((int64_t)*crtot, n);  // at most one record per element
     for (int64_t c0 = (int64_t)blockIdx.x * (U * W); c0 < total; c0 += (int64_t)gridDim.x * (U * W)) {
         const int64_t r0 = c0 + threadIdx.x;
-        int64_t slot[U], c[U], o[U];
+        int64_t sl[U], cc[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int64_t r = r0 + q * W;
-            slot[q] = r < total ? cr_slot[r] : -1;
-            c[q] = r < total ? cr_c[r] : -1;
+            sl[q] = r < total ? cr_slot[r] : -1;
+            cc[q] = r < total ? cr_c[r] : -1;
         }
+        int32_t ui[U];
+        V part[U], x1[U], x2[U], x3[U], x4[U];
+        bool ok[U], ne[U], mid[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            o[q] = -1;
-            if (slot[q] < 0 || c[q] < 0 || c[q] >= n || slot[q] / T >= c[q] / T) continue;
-            o[q] = (int64_t)((uint32_t)U_idx[slot[q]] & ~BLEND_BIT);
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (o[q] < 0 || o[q] >= n) continue;
             const int64_t r = r0 + q * W;
-            const int64_t Q = c[q] / T, R = slot[q] / T;
-            V u = unite(Pay<V>::ld(U_suf, slot[q]), Pay<V>::ld(cr_pre, r));
-            u = unite(u, range_union<V>(upre, usuf, sp, spb, M, nb, R + 1, Q - 1));
-            sink.emit(o[q], u);
-            sink.emit(c[q], u);
+            ok[q] = sl[q] >= 0 && sl[q] < M * T && cc[q] >= 0 && cc[q] < n && sl[q] / T < cc[q] / T;
+            const int64_t s0 = ok[q] ? sl[q] : 0;
+            ui[q] = U_idx[s0];
+            part[q] = unite(Pay<V>::ld(U_suf, s0), Pay<V>::ld(cr_pre, ok[q] ? r : 0));
+            // whole partitions strictly between: [a, b]
+            const int64_t a = ok[q] ? sl[q] / T + 1 : 1, b = ok[q] ? cc[q] / T - 1 : 0;
+            ne[q] = a <= b;
+            const int64_t ba = a / UB, bb = b / UB;
+            const bool same = ba == bb;
+            const int64_t len = ne[q] ? b - a + 1 : 1;
+            const int ls = min(63 - __clzll((unsigned long long)len), UBL - 1);
+            const void *p1 = same ? spb : usuf;
+            const void *p2 = same ? spb : upre;
+            const int64_t i1 = !ne[q] ? 0 : same ? ls * M + a : a;
+            const int64_t i2 = !ne[q] ? 0 : same ? ls * M + b - ((int64_t)1 << ls) + 1 : b;
+            const int64_t l0 = ba + 1, l1 = bb - 1;
+            mid[q] = ne[q] && !same && l0 <= l1;
+            const int lm = mid[q] ? 63 - __clzll((unsigned long long)(l1 - l0 + 1)) : 0;
+            const int64_t i3 = mid[q] ? lm * nb + l0 : 0;
+            const int64_t i4 = mid[q] ? lm * nb + l1 - ((int64_t)1 << lm) + 1 : 0;
+            x1[q] = Pay<V>::ld(p1, i1);
+            x2[q] = Pay<V>::ld(p2, i2);
+            x3[q] = Pay<V>::ld(sp, i3);
+            x4[q] = Pay<V>::ld(sp, i4);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t o = (int64_t)((uint32_t)ui[q] & ~BLEND_BIT);
+            if (!ok[q] || o >= n) continue;
+            V u = part[q];
+            if (ne[q]) u = unite(u, unite(x1[q], x2[q]));
+            if (mid[q]) u = unite(u, unite(x3[q], x4[q]));
+            sink.emit(o, u);
+            sink.emit(cc[q], u);
         }
     }
 }
