@@ -417,9 +417,10 @@ __device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[KK], uint32_t rm
 }
 
 // ------------------------------------------------- LDS min tree over W ints
-// mt[W + i] = leaf i; mt[x] = min(mt[2x], mt[2x+1]) for 1 <= x < W.
-// Thread t supplies leaf t.  The levels inside a wave are formed with
-// butterfly shuffles; only the NWAVE-wide top needs LDS.  Two barriers.
+// mt[W + i] = leaf i; mt[x] = min(mt[2x], mt[2x+1]) for NWAVE <= x < W
+// (down to one node per wave; see mintree_node for the nodes above).
+// Thread t supplies leaf t.  The levels are formed with DPP row shifts and
+// broadcasts inside each wave.  One barrier.
 __device__ __forceinline__ void mintree_build(int *mt, int v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
     mt[W + t] = v;
@@ -438,9 +439,16 @@ __device__ __forceinline__ void mintree_build(int *mt, int v) {
     v = min(v, dmov<dpp::BC31, 0xC>(v, v));
     if (lane == 63) mt[(W + t) >> 6] = v;
     __syncthreads();
-    if (t == 0)
-        for (int x = NWAVE - 1; x >= 1; --x) mt[x] = min(mt[2 * x], mt[2 * x + 1]);
-    __syncthreads();
+}
+
+// A min-tree node; nodes above the wave level (index < NWAVE) are not
+// stored and come from the wave nodes below them.
+__device__ __forceinline__ int mintree_node(const int *mt, int x) {
+    static_assert(NWAVE == 4, "nodes above the wave level are spelled out for four waves");
+    if (x >= NWAVE) return mt[x];
+    if (x == 2) return min(mt[4], mt[5]);
+    if (x == 3) return min(mt[6], mt[7]);
+    return min(min(mt[4], mt[5]), min(mt[6], mt[7]));
 }
 
 // The wave levels of a union tree of boxes over the W threads: leaves at
@@ -469,27 +477,14 @@ __device__ __forceinline__ void uniontree_wave(V *ut, V v) {
 __device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int64_t v) {
     int x = W + t;
     while (x > 1) {
-        if ((x & 1) && (int64_t)mt[x - 1] < v) {
+        if ((x & 1) && (int64_t)mintree_node(mt, x - 1) < v) {
             x = x - 1;
-            while (x < W) x = ((int64_t)mt[2 * x + 1] < v) ? 2 * x + 1 : 2 * x;
+            while (x < W) x = ((int64_t)mintree_node(mt, 2 * x + 1) < v) ? 2 * x + 1 : 2 * x;
             return x - W;
         }
         x >>= 1;
     }
     return -1;
-}
-
-// min over leaves [lo, hi] (INT32_MAX if empty)
-__device__ __forceinline__ int mintree_range_min(const int *mt, int lo, int hi) {
-    int r = INT32_MAX;
-    if (lo > hi) return r;
-    int l = lo + W, h = hi + W + 1;
-    while (l < h) {
-        if (l & 1) r = min(r, mt[l++]);
-        if (h & 1) r = min(r, mt[--h]);
-        l >>= 1, h >>= 1;
-    }
-    return r;
 }
 
 // Union over leaves [lo, hi] of a tree built by uniontree_wave, for

@@ -418,6 +418,8 @@ struct ResolveSmem {
     static_assert(K <= 4 && T < 0xFFFF, "tinfo packs 4-bit masks and 16-bit entries");
     int mt[2 * W];
     int jptr[W];
+    V jval2[BOXES ? W : 1];  // second buffer of the cross-wave pointer jumping
+    int jptr2[W];
     SegU sh_seg[NWAVE];
     V wtot[NWAVE];  // union of each wave's leaves
     int wmin[NWAVE];  // lowest level each wave reaches
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
     int wmin0;
     int premin = wave_excl_scan(cm, MinOp{}, INT32_MAX, &wmin0);  // lowest level of earlier lanes
-    mintree_build(sm.mt, cm);  // its barriers also publish everything above
+    mintree_build(sm.mt, cm);  // its barrier also publishes everything above
 
     // levels at or below `lowtop` are held by no earlier thread of this
     // partition: they come from earlier partitions (the LDS table).
@@ -567,17 +569,21 @@ __global__ __launch_bounds__(W) void k_resolve(
                 ptr = pp;
             }
         }
+        // Across waves every pointer now leaves its wave, so two doubling
+        // rounds (double-buffered) reach the partition's base for 4 waves.
+        static_assert(NWAVE <= 4, "two doubling rounds cover at most four waves");
         sm.e.w.jval[t] = v;
         sm.jptr[t] = ptr;
-        for (int r = 0; r < NWAVE && __syncthreads_or(ptr >= 0); ++r) {  // also publishes tlink
-            if (ptr >= 0) {
-                v = isect(v, sm.e.w.jval[ptr]);
-                ptr = sm.jptr[ptr];
-            }
-            __syncthreads();
-            sm.e.w.jval[t] = v;
-            sm.jptr[t] = ptr;
+        __syncthreads();  // also publishes tlink
+        if (ptr >= 0) {
+            v = isect(v, sm.e.w.jval[ptr]);
+            ptr = sm.jptr[ptr];
         }
+        sm.jval2[t] = v;
+        sm.jptr2[t] = ptr;
+        __syncthreads();
+        if (ptr >= 0) v = isect(v, sm.jval2[ptr]);
+        sm.e.w.jval[t] = v;  // every read of the first buffer happened before the barrier
         __syncthreads();
     } else {
         __syncthreads();  // publishes tlink
