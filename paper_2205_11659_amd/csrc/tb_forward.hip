@@ -51,95 +51,107 @@ __global__ void k_check_offsets(const int64_t *off, int64_t S, int64_t n, uint32
 }
 
 // ---------------------------------------------------------------- k_reduce
-// One wave per partition: each lane walks RK = T / 64 consecutive elements,
-// so every combine below is a wave-level shuffle scan (no LDS, no barrier).
-// A workgroup holds RW independent waves.
-constexpr int RK = T / WAVE;
-constexpr int RW = 4;
-
+// One workgroup of W threads per partition, K consecutive elements per
+// thread (coalesced loads and stores).  Prefix and suffix bicyclic products
+// over threads come from DPP wave scans plus the four wave totals, so the
+// whole kernel needs two barriers.
 template <bool BOXES, class V>
-__global__ __launch_bounds__(RW * WAVE) void k_reduce(const uint32_t *__restrict__ kind,
-                                                 const float4 *__restrict__ box, int64_t n,
-                                                 const int64_t *__restrict__ off, int64_t S,
-                                                 int4 *__restrict__ pinfo,
-                                                 int32_t *__restrict__ U_idx,
-                                                 void *__restrict__ U_cum) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t P = (int64_t)blockIdx.x * RW + (threadIdx.x >> 6);
-    const int64_t M = (n + T - 1) / T;
-    if (P >= M) return;  // whole wave leaves: no shuffle below sees it
-    const int64_t g0 = P * T + (int64_t)lane * RK;
+__global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
+                                              const float4 *__restrict__ box, int64_t n,
+                                              const int64_t *__restrict__ off, int64_t S,
+                                              int4 *__restrict__ pinfo,
+                                              int32_t *__restrict__ U_idx, void *__restrict__ U_cum) {
+    __shared__ BicR sh_bic[NWAVE];
+    __shared__ V sh_b[NWAVE];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
+    const int64_t P = blockIdx.x;
+    const int64_t g0 = P * T + (int64_t)t * K;
 
-    uint32_t ks[RK];
-    load_kinds<RK>(kind, n, g0, ks);
+    uint32_t ks[K];
+    load_kinds<K>(kind, n, g0, ks);
 #pragma unroll
-    for (int j = 0; j < RK; ++j)
+    for (int j = 0; j < K; ++j)
         if (ks[j] > 4u) ks[j] = LEAF;
-    const uint32_t rm = reset_mask<RK>(off, S, g0);
-    const Walk wk = walk_kinds<RK>(ks, rm);
+    const uint32_t rm = reset_mask<K>(off, S, g0);
+    const Walk wk = walk_kinds<K>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
+    // boxes of this thread's unmatched clip opens, issued before the scans
+    // (those that do not survive the partition are read and dropped)
+    V bxs[K];
+    if (BOXES) {
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+            bxs[p] = (((wk.umask >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::own(box[g0 + p], g0 + p)
+                                                                 : Pay<V>::inf();
+    }
 
-    // prefix: depth at this lane's start; total: the partition's summary
-    BicR tot;
-    const BicR pre = wave_excl_scan(mine, BicROp{}, BicR{0, 0, 0}, &tot);
+    // prefix (earlier threads) and suffix (later threads) products
+    BicR wtot, wtot2;
+    BicR pre = wave_excl_scan(mine, BicROp{}, BicR{0, 0, 0}, &wtot);
+    BicR suf = wave_excl_suffix_scan(mine, BicROp{}, BicR{0, 0, 0}, &wtot2);
+    if (lane == 0) sh_bic[wid] = wtot;
+    __syncthreads();
+    BicR before{0, 0, 0}, after{0, 0, 0}, tot{0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) {
+        const BicR x = sh_bic[w];
+        if (w < wid) before = bicr(before, x);
+        tot = bicr(tot, x);
+    }
+#pragma unroll
+    for (int w = NWAVE - 1; w >= 0; --w)
+        if (w > wid) after = bicr(sh_bic[w], after);
+    pre = bicr(before, pre);
+    suf = bicr(suf, after);
     const int D = pre.r ? pre.b : pre.b - pre.a;  // partition-relative unless a reset came first
     const int base = wk.rs ? 0 : D - wk.a;
     const int baseP = tot.r ? 0 : -tot.a;
-    // suffix (later lanes): how many of this lane's unmatched opens they pop
-    BicR rt;
-    const BicR suf = wave_excl_suffix_scan(mine, BicROp{}, BicR{0, 0, 0}, &rt);
+    // later threads pop the last `suf.a` of this thread's unmatched opens
     const int b = mine.b;
     const int ns = suf.r ? 0 : (b > suf.a ? b - suf.a : 0);
 
-    // boxes of the surviving clip opens: all gathers are issued before any is used
-    uint32_t need = 0;
+    // clip prefix over the partition's surviving opens
+    uint32_t surv = 0;  // positions of this thread's surviving unmatched opens
     {
         int jj = 0;
 #pragma unroll
-        for (int p = 0; p < RK; ++p) {
+        for (int p = 0; p < K; ++p) {
             if ((wk.umask >> p) & 1u) {
-                if (jj < ns && ks[p] == BCLIP) need |= 1u << p;
+                if (jj < ns) surv |= 1u << p;
                 ++jj;
             }
         }
     }
-    V bxs[RK];
+    V cum = Pay<V>::inf();
     if (BOXES) {
+        V agg = Pay<V>::inf();
 #pragma unroll
-        for (int p = 0; p < RK; ++p) {
-            float4 f = make_float4(-INFINITY, -INFINITY, INFINITY, INFINITY);
-            if ((need >> p) & 1u) f = box[g0 + p];
-            bxs[p] = Pay<V>::own(f, g0 + p);
-        }
-    }
-    // intersection of the surviving clip opens, then its exclusive prefix over lanes
-    V agg = Pay<V>::inf();
-    if (BOXES) {
+        for (int p = 0; p < K; ++p)
+            if ((surv >> p) & 1u) agg = isect(agg, bxs[p]);
+        V wagg;
+        cum = wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &wagg);
+        if (lane == 0) sh_b[wid] = wagg;
+        __syncthreads();
 #pragma unroll
-        for (int p = 0; p < RK; ++p)
-            if ((need >> p) & 1u) agg = isect(agg, bxs[p]);
+        for (int w = 0; w < NWAVE - 1; ++w)
+            if (w < wid) cum = isect(sh_b[w], cum);
     }
-    V aggtot;
-    V cum = BOXES ? wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &aggtot) : Pay<V>::inf();
 
+    const int64_t slot0 = (int64_t)base - baseP;  // first surviving open's slot
     int jj = 0;
 #pragma unroll
-    for (int p = 0; p < RK; ++p) {
-        if (!((wk.umask >> p) & 1u)) continue;
-        if (jj < ns) {
-            const int64_t L = (int64_t)base + 1 + jj;
-            const int64_t slot = L - baseP - 1;
-            if (slot >= 0 && slot < T) {
-                U_idx[P * T + slot] = (int32_t)((uint32_t)(g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
-                if (BOXES) {
-                    if ((need >> p) & 1u) cum = isect(cum, bxs[p]);
-                    Pay<V>::st(U_cum, P * T + slot, cum);
-                }
-            }
-        }
+    for (int p = 0; p < K; ++p) {
+        if (!((surv >> p) & 1u)) continue;
+        const int64_t slot = slot0 + jj;
         ++jj;
+        if (slot < 0 || slot >= T) continue;
+        U_idx[P * T + slot] = (int32_t)((uint32_t)(g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
+        if (BOXES) {
+            cum = isect(cum, bxs[p]);  // the identity unless a clip
+            Pay<V>::st(U_cum, P * T + slot, cum);
+        }
     }
-    if (lane == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
+    if (t == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
 }
 
 // ------------------------------------------------------------ spine kernels
@@ -1139,7 +1151,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     int *crtot = (int *)(w + L.crtot);
     int32_t *U_idx = (int32_t *)(w + L.U_idx);
     void *U_cum = w + L.U_cum;
-    k_reduce<BOXES, V><<<(unsigned)((M + RW - 1) / RW), RW * WAVE, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
+    k_reduce<BOXES, V><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
