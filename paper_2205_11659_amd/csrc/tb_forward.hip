@@ -434,7 +434,6 @@ struct ResolveSmem {
     int jptr2[W];
     SegU sh_seg[NWAVE];
     V wtot[NWAVE];  // union of each wave's leaves
-    int wmin[NWAVE];  // lowest level each wave reaches
 };
 
 template <bool BOXES, class V, class SINK>
@@ -490,9 +489,11 @@ __global__ __launch_bounds__(W) void k_resolve(
         g_ctx[q] = Pay<V>::inf();
         const int x = t + q * W;
         const int L = preM + x;
-        if (x > aP || L < 1) continue;
-        int64_t R;
-        const int64_t slot = incoming_slot(L, sm.runs, nruns, head, part, M, &R);
+        if (x > aP) continue;
+        int64_t R = -1, slot = -1;
+        if (L >= 1) slot = incoming_slot(L, sm.runs, nruns, head, part, M, &R);
+        // if level L is popped here, that pop is close record aP - x
+        if (BOXES && x >= 1 && (uint32_t)(rbase + aP - x) < un) cr_slot[rbase + aP - x] = (int32_t)slot;
         if (slot < 0) continue;
         g_idx[q] = U_idx[slot];
         if (BOXES) g_ctx[q] = isect(Pay<V>::ld(U_cum, slot), Pay<V>::ld(base_ctx, R));
@@ -545,6 +546,13 @@ __global__ __launch_bounds__(W) void k_resolve(
     for (int w = 0; w < NWAVE - 1; ++w)
         if (w < (t >> 6)) premin = min(premin, sm.mt[NWAVE + w]);  // wave nodes of the min tree
     const int lowtop = min(premin, Dt);
+    // lowest level any later thread reaches: an unmatched open of this thread
+    // at a level not above it survives the partition
+    int wmin1;
+    int sufmin = wave_excl_suffix_scan(cm, MinOp{}, INT32_MAX, &wmin1);
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w)
+        if (w > (t >> 6)) sufmin = min(sufmin, sm.mt[NWAVE + w]);
     // owner links between threads: the entry just below a thread's lowest
     // level belongs to the nearest earlier thread with a smaller lowest level
     const int tl = wk.rs ? -1 : mintree_prev_less(sm.mt, t, cm);
@@ -714,6 +722,12 @@ __global__ __launch_bounds__(W) void k_resolve(
         const bool rootclose = isclose && tp < 0 && rseen;  // closes below its scene's root
         const bool rclose = isclose && tp < 0 && !rseen;    // closes a level held before this thread
         const bool rok = rclose && dep > 0 && cur_idx >= 0;
+        // pops of levels held by earlier partitions leave a close record, and
+        // the cross-partition kernel writes both rows and both match entries
+        const int ci = dP - dep;
+        const bool rec = BOXES && rclose && cur_own < 0 && ci >= 0 && ci < aP && (uint32_t)(rbase + ci) < un;
+        // so does a clip open that survives this partition
+        const bool sclip = BOXES && k == BCLIP && ((wk.umask >> j) & 1u) && dep + 1 <= sufmin;
         const int tps = tp < 0 ? 0 : tp;
         const uint32_t pbit = lclose ? (1u << tps) : 0u;
         if (BOXES) {
@@ -729,17 +743,17 @@ __global__ __launch_bounds__(W) void k_resolve(
         errs |= (real && (rootclose || (rclose && !rok))) ? ST_UNBAL << (4 * j) : 0u;
         leafm |= isleaf ? bit : 0u;
         clipm |= k == BCLIP ? bit : 0u;
-        keep |= (isleaf || k == BCLIP || (k == ECLIP && (lclose || rok))) ? bit : 0u;
+        keep |= (isleaf || (k == BCLIP && !sclip) || (k == ECLIP && (lclose || (rok && !rec)))) ? bit : 0u;
         keep |= (lclose && k == EBLEND) ? (bit | pbit) : 0u;
         lbm |= (lclose && k == EBLEND) ? bit : 0u;
         lbp[j] = tps;
-        mkeep |= (isleaf || lclose || rok) ? bit : 0u;
+        mkeep |= (isleaf || lclose || (rok && !rec)) ? bit : 0u;
         mkeep |= pbit;
         mv[j] = lclose ? (int32_t)(g0 + tps - soff) : rok ? (int32_t)(cur_idx - soff) : -1;
 #pragma unroll
         for (int q = 0; q < j; ++q)
             if (lclose && q == tp) mv[q] = (int32_t)(i - soff);
-        if (rok && match && real && (uint32_t)cur_idx < un) match[cur_idx] = (int32_t)(i - soff);
+        if (rok && !rec && match && real && (uint32_t)cur_idx < un) match[cur_idx] = (int32_t)(i - soff);
         if (BOXES && rok && k == EBLEND && real) {
             defmask |= bit;
             def_L[j] = dep;
@@ -747,20 +761,7 @@ __global__ __launch_bounds__(W) void k_resolve(
             def_pos[j] = cur_pos;
             def_ent[j] = cur_ent;
         }
-        // every pop of a partition-incoming level leaves a record
-        if (BOXES && rclose && cur_own < 0) {
-            const int L = dep;
-            const int ci = dP - L;
-            if (ci >= 0 && ci < aP && (uint32_t)(rbase + ci) < un) {
-                int32_t sl = -1;
-                if (k == EBLEND && real && L >= 1 && cur_idx >= 0) {
-                    int64_t R;
-                    sl = (int32_t)incoming_slot(L, sm.runs, nruns, head, part, M, &R);
-                }
-                cr_slot[rbase + ci] = sl;
-                cr_c[rbase + ci] = (int32_t)i;
-            }
-        }
+        if (rec) cr_c[rbase + ci] = (int32_t)i;  // its slot was written by the gather
         mask = isopen ? (mask | bit) : (mask & ~pbit);
         dep += isopen ? 1 : (lclose || rclose) ? -1 : 0;
     }
@@ -810,14 +811,9 @@ __global__ __launch_bounds__(W) void k_resolve(
     const V wpre = wave_excl_scan(ttot, UniteOp{}, Pay<V>::empty(), &wtot_u);
     V wsuf_dummy;
     const V wsuf = wave_excl_suffix_scan(ttot, UniteOp{}, Pay<V>::empty(), &wsuf_dummy);
-    int wmin;
-    const int wsufmin = wave_excl_suffix_scan(cm, MinOp{}, INT32_MAX, &wmin);
     __syncthreads();  // the walk's reads of the early tables and cx are done
     uniontree_wave(ut, ttot);
-    if (lane == 0) {
-        sm.wtot[wid] = wtot_u;
-        sm.wmin[wid] = wmin;
-    }
+    if (lane == 0) sm.wtot[wid] = wtot_u;
     {  // suffix unions after each of this thread's unmatched opens
         V suf = Pay<V>::empty();
         int e = ub + __popc(wk.umask);
@@ -832,15 +828,11 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
     __syncthreads();
     V pre_t = wpre, suf_t = wsuf, all = Pay<V>::empty();
-    int sufmin = wsufmin;
 #pragma unroll
     for (int w = 0; w < NWAVE; ++w) {
         const V x = sm.wtot[w];
         if (w < wid) pre_t = unite(pre_t, x);
-        if (w > wid) {
-            suf_t = unite(suf_t, x);
-            sufmin = min(sufmin, sm.wmin[w]);
-        }
+        if (w > wid) suf_t = unite(suf_t, x);
         all = unite(all, x);
     }
     // closes of blends opened in an earlier partition: the prefix part
@@ -953,7 +945,10 @@ __global__ __launch_bounds__(1024) void k_usparse(void *__restrict__ sp, int64_t
 
 template <class V, class SINK>
 __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int64_t n,
+                                             const int64_t *__restrict__ off, int64_t S,
                                              const int32_t *__restrict__ U_idx,
+                                             const void *__restrict__ U_cum,
+                                             const void *__restrict__ base_ctx,
                                              const void *__restrict__ U_suf,
                                              const int32_t *__restrict__ cr_slot,
                                              const int32_t *__restrict__ cr_c,
@@ -962,12 +957,17 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
                                              const void *__restrict__ usuf,
                                              const void *__restrict__ sp,
                                              const void *__restrict__ spb, int64_t M, int64_t nb,
-                                             SINK sink) {
-    // one thread per close record; records are dense, their count is on the
-    // device.  A workgroup takes contiguous chunks of U*W records (few pages
-    // per wave), U records per thread.  After the records themselves, every
-    // load of a record is issued at once: invalid lanes read entry 0 and
-    // discard it, so no load waits behind a branch.
+                                             int32_t *__restrict__ match, SINK sink) {
+    // One thread per close record: a close whose open lies in an earlier
+    // partition.  Both rows and both match entries of the pair are written
+    // here, so consecutive records write consecutive rows.  A clip pair's box
+    // is the open's full clip context (its partition-local prefix intersected
+    // with the context at that partition's base); a blend pair's is the union
+    // of the open's suffix, the whole partitions between and the close's
+    // prefix.  Records are dense and their count is on the device.  A
+    // workgroup takes contiguous chunks of U*W records, U per thread; after
+    // the records themselves every load is issued at once (unused lanes read
+    // entry 0 and discard it).
     constexpr int U = sizeof(V) <= 16 ? 4 : 2;
     const int64_t total = min((int64_t)*crtot, n);  // at most one record per element
     for (int64_t c0 = (int64_t)blockIdx.x * (U * W); c0 < total; c0 += (int64_t)gridDim.x * (U * W)) {
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
             cc[q] = r < total ? cr_c[r] : -1;
         }
         int32_t ui[U];
-        V part[U], x1[U], x2[U], x3[U], x4[U];
+        V part[U], cl[U], x1[U], x2[U], x3[U], x4[U];
         bool ok[U], ne[U], mid[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -988,6 +988,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
             ok[q] = sl[q] >= 0 && sl[q] < M * T && cc[q] >= 0 && cc[q] < n && sl[q] / T < cc[q] / T;
             const int64_t s0 = ok[q] ? sl[q] : 0;
             ui[q] = U_idx[s0];
+            cl[q] = isect(Pay<V>::ld(U_cum, s0), Pay<V>::ld(base_ctx, s0 / T));
             part[q] = unite(Pay<V>::ld(U_suf, s0), Pay<V>::ld(cr_pre, ok[q] ? r : 0));
             // whole partitions strictly between: [a, b]
             const int64_t a = ok[q] ? sl[q] / T + 1 : 1, b = ok[q] ? cc[q] / T - 1 : 0;
@@ -1014,11 +1015,21 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
         for (int q = 0; q < U; ++q) {
             const int64_t o = (int64_t)((uint32_t)ui[q] & ~BLEND_BIT);
             if (!ok[q] || o >= n) continue;
-            V u = part[q];
-            if (ne[q]) u = unite(u, unite(x1[q], x2[q]));
-            if (mid[q]) u = unite(u, unite(x3[q], x4[q]));
+            V u;
+            if ((uint32_t)ui[q] & BLEND_BIT) {
+                u = part[q];
+                if (ne[q]) u = unite(u, unite(x1[q], x2[q]));
+                if (mid[q]) u = unite(u, unite(x3[q], x4[q]));
+            } else {
+                u = canon(cl[q]);
+            }
             sink.emit(o, u);
             sink.emit(cc[q], u);
+            if (match) {
+                const int64_t soff = off ? off[scene_of(off, S, cc[q])] : 0;
+                match[o] = (int32_t)(cc[q] - soff);
+                match[cc[q]] = (int32_t)(o - soff);
+            }
         }
     }
 }
@@ -1197,8 +1208,9 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
         k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp, spb);
         k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
         const int64_t gx = min((int64_t)(n + W - 1) / W, (int64_t)256 * 32);
-        k_cross<V, SINK><<<(unsigned)gx, W, 0, st>>>(crtot, n, U_idx, U_suf, cr_slot, cr_c, cr_pre,
-                                                      upre, usuf, sp, spb, M, L.nb, sink);
+        k_cross<V, SINK><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_cum, jv[cur], U_suf,
+                                                      cr_slot, cr_c, cr_pre, upre, usuf, sp, spb, M,
+                                                      L.nb, match, sink);
     }
     return hipGetLastError();
 }
