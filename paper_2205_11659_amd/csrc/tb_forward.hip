@@ -761,7 +761,9 @@ __global__ __launch_bounds__(W) void k_resolve(
             def_pos[j] = cur_pos;
             def_ent[j] = cur_ent;
         }
-        if (rec) cr_c[rbase + ci] = (int32_t)i;  // its slot was written by the gather
+        // the close's position, with the top bit set for a blend; the slot was
+        // written by the gather
+        if (rec) cr_c[rbase + ci] = (int32_t)(i | (k == EBLEND ? 0x80000000u : 0u));
         mask = isopen ? (mask | bit) : (mask & ~pbit);
         dep += isopen ? 1 : (lclose || rclose) ? -1 : 0;
     }
@@ -977,7 +979,13 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
         for (int q = 0; q < U; ++q) {
             const int64_t r = r0 + q * W;
             sl[q] = r < total ? cr_slot[r] : -1;
-            cc[q] = r < total ? cr_c[r] : -1;
+            cc[q] = r < total ? (int64_t)(uint32_t)cr_c[r] : -1;
+        }
+        bool bl[U];  // blend pair (the close record's top bit)
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            bl[q] = cc[q] >= 0 && (cc[q] & 0x80000000ll);
+            if (cc[q] >= 0) cc[q] &= 0x7FFFFFFFll;
         }
         int32_t ui[U];
         V part[U], cl[U], x1[U], x2[U], x3[U], x4[U];
@@ -988,10 +996,12 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
             ok[q] = sl[q] >= 0 && sl[q] < M * T && cc[q] >= 0 && cc[q] < n && sl[q] / T < cc[q] / T;
             const int64_t s0 = ok[q] ? sl[q] : 0;
             ui[q] = U_idx[s0];
-            cl[q] = isect(Pay<V>::ld(U_cum, s0), Pay<V>::ld(base_ctx, s0 / T));
-            part[q] = unite(Pay<V>::ld(U_suf, s0), Pay<V>::ld(cr_pre, ok[q] ? r : 0));
+            // only the loads this kind of pair uses (the others read entry 0)
+            const int64_t sc = bl[q] ? 0 : s0, sb = bl[q] ? s0 : 0;
+            cl[q] = isect(Pay<V>::ld(U_cum, sc), Pay<V>::ld(base_ctx, sc / T));
+            part[q] = unite(Pay<V>::ld(U_suf, sb), Pay<V>::ld(cr_pre, ok[q] && bl[q] ? r : 0));
             // whole partitions strictly between: [a, b]
-            const int64_t a = ok[q] ? sl[q] / T + 1 : 1, b = ok[q] ? cc[q] / T - 1 : 0;
+            const int64_t a = ok[q] && bl[q] ? sl[q] / T + 1 : 1, b = ok[q] && bl[q] ? cc[q] / T - 1 : 0;
             ne[q] = a <= b;
             const int64_t ba = a / UB, bb = b / UB;
             const bool same = ba == bb;
@@ -1016,7 +1026,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
             const int64_t o = (int64_t)((uint32_t)ui[q] & ~BLEND_BIT);
             if (!ok[q] || o >= n) continue;
             V u;
-            if ((uint32_t)ui[q] & BLEND_BIT) {
+            if (bl[q]) {
                 u = part[q];
                 if (ne[q]) u = unite(u, unite(x1[q], x2[q]));
                 if (mid[q]) u = unite(u, unite(x3[q], x4[q]));
