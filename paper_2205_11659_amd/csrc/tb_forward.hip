@@ -671,10 +671,11 @@ __global__ __launch_bounds__(W) void k_resolve(
                 const int x = dep - preM;
                 if (x >= 0 && x <= aP) {
                     const int u = sm.e.w.inc_idx[x];
+                    const V c = BOXES ? sm.cx[x] : Pay<V>::inf();  // read together with u
                     if (u != -1) {
                         cur_idx = (int)((uint32_t)u & ~BLEND_BIT);
                         cur_kind = ((uint32_t)u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
-                        if (BOXES) cur_ctx = sm.cx[x];
+                        cur_ctx = c;
                     }
                 }
             } else if (dep > lowtop) {
