@@ -626,8 +626,12 @@ __global__ __launch_bounds__(W) void k_resolve(
     bool rseen = false;
     int dep = Dt;
     V octx[K], res[K];
-    int mv[K], lbp[K], def_own[K], def_pos[K], def_ent[K];
-    int def_L[K];
+    int mv[K];
+    uint32_t lbp = 0;  // 2 bits per position: the local open a blend close matches
+    // per deferred blend close, packed: owner thread + 1 (0 = an earlier
+    // partition), its position and cx entry; or, for an earlier partition,
+    // the close record's index within this partition
+    uint32_t dfw[K];
     // the stack entry at level `cur_L` seen from this thread's start; the
     // levels asked for only decrease, so the owner search moves left along
     // owner links from the previous thread
@@ -640,9 +644,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         octx[j] = Pay<V>::inf();
         res[j] = Pay<V>::empty();
         mv[j] = -1;
-        lbp[j] = 0;
-        def_own[j] = def_pos[j] = def_ent[j] = -1;
-        def_L[j] = 0;
+        dfw[j] = 0;
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < K; ++j) {
@@ -747,7 +749,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         keep |= (isleaf || (k == BCLIP && !sclip) || (k == ECLIP && (lclose || (rok && !rec)))) ? bit : 0u;
         keep |= (lclose && k == EBLEND) ? (bit | pbit) : 0u;
         lbm |= (lclose && k == EBLEND) ? bit : 0u;
-        lbp[j] = tps;
+        lbp |= (uint32_t)tps << (2 * j);
         mkeep |= (isleaf || lclose || (rok && !rec)) ? bit : 0u;
         mkeep |= pbit;
         mv[j] = lclose ? (int32_t)(g0 + tps - soff) : rok ? (int32_t)(cur_idx - soff) : -1;
@@ -757,10 +759,8 @@ __global__ __launch_bounds__(W) void k_resolve(
         if (rok && !rec && match && real && (uint32_t)cur_idx < un) match[cur_idx] = (int32_t)(i - soff);
         if (BOXES && rok && k == EBLEND && real) {
             defmask |= bit;
-            def_L[j] = dep;
-            def_own[j] = cur_own;
-            def_pos[j] = cur_pos;
-            def_ent[j] = cur_ent;
+            dfw[j] = cur_own >= 0 ? (uint32_t)(cur_own + 1) | ((uint32_t)cur_pos << 9) | ((uint32_t)cur_ent << 11)
+                                  : (uint32_t)(dP - dep) << 11;
         }
         // the close's position, with the top bit set for a blend; the slot was
         // written by the gather
@@ -780,7 +780,7 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
         for (int j = 1; j < K; ++j) {
             if (!((lbm >> j) & 1u)) continue;
-            const int p = lbp[j];
+            const int p = (lbp >> (2 * j)) & 3u;
             V u = Pay<V>::empty();
 #pragma unroll
             for (int q = 1; q < j; ++q)
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!((defmask >> j) & 1u)) continue;
-        if (def_own[j] >= 0) {
+        if (dfw[j] & 0x1FFu) {  // owner thread in this partition
             dloc |= 1u << j;
             continue;
         }
@@ -851,8 +851,8 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
         for (int q = 0; q < j; ++q)
             if ((leafm >> q) & 1u) pre = unite(pre, res[q]);
-        const int ci = dP - def_L[j];
-        if (ci >= 0 && ci < aP && (uint32_t)(rbase + ci) < un)
+        const int ci = (int)(dfw[j] >> 11);
+        if (ci < aP && (uint32_t)(rbase + ci) < un)
             Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
     }
     // closes of blends opened in an earlier thread of this partition, taken
@@ -861,17 +861,14 @@ __global__ __launch_bounds__(W) void k_resolve(
         if (!dloc) continue;
         const int j = __builtin_ctz(dloc);
         dloc &= dloc - 1;
-        int s = 0, ent = 0, pos = 0;
+        uint32_t w = 0;
         V pre = Pay<V>::empty();
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            if (q == j) {
-                s = def_own[q];
-                ent = def_ent[q];
-                pos = def_pos[q];
-            }
+            if (q == j) w = dfw[q];
             if (q < j && ((leafm >> q) & 1u)) pre = unite(pre, res[q]);
         }
+        const int s = (int)(w & 0x1FFu) - 1, pos = (int)((w >> 9) & 3u), ent = (int)(w >> 11);
         const V u = unite(unite(sm.cx[ent], uniontree_inner(ut, s + 1, t - 1)), pre);
         sink.emit(g0 + j, u);
         sink.emit(p0 + (uint32_t)s * K + pos, u);
