@@ -96,14 +96,19 @@ def _as_box(box, n):
     return box.contiguous()
 
 
-def tb_match(kind, pm=True):
-    """Matching only: returns (match int32[n], pm int32[n] or None, status int32[1])."""
+def tb_match(kind, pm=True, match=None, status=None):
+    """Matching only: returns (match int32[n], pm int32[n] or None, status int32[1]).
+    `pm` may be True/False or a preallocated int32 tensor; `match` and
+    `status` may be preallocated too."""
     kind = _as_kind(kind)
     n = kind.numel()
     dev = kind.device
-    match = torch.empty(n, dtype=torch.int32, device=dev)
-    pmo = torch.empty(n, dtype=torch.int32, device=dev) if pm else None
-    status = torch.empty(1, dtype=torch.int32, device=dev)
+    match = torch.empty(n, dtype=torch.int32, device=dev) if match is None else match
+    if isinstance(pm, torch.Tensor):
+        pmo = pm
+    else:
+        pmo = torch.empty(n, dtype=torch.int32, device=dev) if pm else None
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
     ws, wsb = workspace(OP_MATCH, n, 1, dev)
     _check(lib().tb_match(_ptr(kind), n, _ptr(match), _ptr(pmo), ctypes.c_void_p(ws), wsb,
                           _ptr(status), _stream()))

@@ -416,36 +416,40 @@ __device__ __forceinline__ Walk walk_kinds(const uint32_t (&ks)[KK], uint32_t rm
     return {a, mask, rs};
 }
 
-// ------------------------------------------------- LDS min tree over W ints
-// mt[W + i] = leaf i; mt[x] = min(mt[2x], mt[2x+1]) for NWAVE <= x < W
+// ------------------------------------------------ LDS min tree over WW ints
+// mt[WW + i] = leaf i; mt[x] = min(mt[2x], mt[2x+1]) for WW/64 <= x < WW
 // (down to one node per wave; see mintree_node for the nodes above).
 // Thread t supplies leaf t.  The levels are formed with DPP row shifts and
 // broadcasts inside each wave.  One barrier.
+template <int WW = W>
 __device__ __forceinline__ void mintree_build(int *mt, int v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
-    mt[W + t] = v;
+    mt[WW + t] = v;
     // after step l, a lane whose low l bits are all set holds the min of its
     // aligned group of 2^l lanes (out-of-pattern lanes combine with themselves)
     v = min(v, dmov<dpp::SHR1>(v, v));
-    if ((lane & 1) == 1) mt[(W + t) >> 1] = v;
+    if ((lane & 1) == 1) mt[(WW + t) >> 1] = v;
     v = min(v, dmov<dpp::SHR2>(v, v));
-    if ((lane & 3) == 3) mt[(W + t) >> 2] = v;
+    if ((lane & 3) == 3) mt[(WW + t) >> 2] = v;
     v = min(v, dmov<dpp::SHR4>(v, v));
-    if ((lane & 7) == 7) mt[(W + t) >> 3] = v;
+    if ((lane & 7) == 7) mt[(WW + t) >> 3] = v;
     v = min(v, dmov<dpp::SHR8>(v, v));
-    if ((lane & 15) == 15) mt[(W + t) >> 4] = v;
+    if ((lane & 15) == 15) mt[(WW + t) >> 4] = v;
     v = min(v, dmov<dpp::BC15, 0xA>(v, v));
-    if ((lane & 31) == 31) mt[(W + t) >> 5] = v;
+    if ((lane & 31) == 31) mt[(WW + t) >> 5] = v;
     v = min(v, dmov<dpp::BC31, 0xC>(v, v));
-    if (lane == 63) mt[(W + t) >> 6] = v;
+    if (lane == 63) mt[(WW + t) >> 6] = v;
     __syncthreads();
 }
 
-// A min-tree node; nodes above the wave level (index < NWAVE) are not
+// A min-tree node; nodes above the wave level (index < WW/64) are not
 // stored and come from the wave nodes below them.
+template <int WW = W>
 __device__ __forceinline__ int mintree_node(const int *mt, int x) {
-    static_assert(NWAVE == 4, "nodes above the wave level are spelled out for four waves");
-    if (x >= NWAVE) return mt[x];
+    constexpr int NW = WW / WAVE;
+    static_assert(NW == 1 || NW == 2 || NW == 4, "one, two or four waves");
+    if (x >= NW) return mt[x];
+    if (NW == 2) return min(mt[2], mt[3]);  // x == 1
     if (x == 2) return min(mt[4], mt[5]);
     if (x == 3) return min(mt[6], mt[7]);
     return min(min(mt[4], mt[5]), min(mt[6], mt[7]));
@@ -474,13 +478,14 @@ __device__ __forceinline__ void uniontree_wave(V *ut, V v) {
 }
 
 // rightmost leaf s < t with leaf value < v, or -1
+template <int WW = W>
 __device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int64_t v) {
-    int x = W + t;
+    int x = WW + t;
     while (x > 1) {
-        if ((x & 1) && (int64_t)mintree_node(mt, x - 1) < v) {
+        if ((x & 1) && (int64_t)mintree_node<WW>(mt, x - 1) < v) {
             x = x - 1;
-            while (x < W) x = ((int64_t)mintree_node(mt, 2 * x + 1) < v) ? 2 * x + 1 : 2 * x;
-            return x - W;
+            while (x < WW) x = ((int64_t)mintree_node<WW>(mt, 2 * x + 1) < v) ? 2 * x + 1 : 2 * x;
+            return x - WW;
         }
         x >>= 1;
     }

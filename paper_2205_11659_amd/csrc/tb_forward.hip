@@ -55,32 +55,33 @@ __global__ void k_check_offsets(const int64_t *off, int64_t S, int64_t n, uint32
 // thread (coalesced loads and stores).  Prefix and suffix bicyclic products
 // over threads come from DPP wave scans plus the four wave totals, so the
 // whole kernel needs two barriers.
-template <bool BOXES, class V>
-__global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
+template <bool BOXES, class V, int KK>
+__global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ kind,
                                               const float4 *__restrict__ box, int64_t n,
                                               const int64_t *__restrict__ off, int64_t S,
                                               int4 *__restrict__ pinfo,
                                               int32_t *__restrict__ U_idx, void *__restrict__ U_cum) {
-    __shared__ BicR sh_bic[NWAVE];
-    __shared__ V sh_b[NWAVE];
+    constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
+    __shared__ BicR sh_bic[NW];
+    __shared__ V sh_b[NW];
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
     const int64_t P = blockIdx.x;
-    const int64_t g0 = P * T + (int64_t)t * K;
+    const int64_t g0 = P * T + (int64_t)t * KK;
 
-    uint32_t ks[K];
-    load_kinds<K>(kind, n, g0, ks);
+    uint32_t ks[KK];
+    load_kinds<KK>(kind, n, g0, ks);
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+    for (int j = 0; j < KK; ++j)
         if (ks[j] > 4u) ks[j] = LEAF;
-    const uint32_t rm = reset_mask<K>(off, S, g0);
-    const Walk wk = walk_kinds<K>(ks, rm);
+    const uint32_t rm = reset_mask<KK>(off, S, g0);
+    const Walk wk = walk_kinds<KK>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
     // boxes of this thread's unmatched clip opens, issued before the scans
     // (those that do not survive the partition are read and dropped)
-    V bxs[K];
+    V bxs[KK];
     if (BOXES) {
 #pragma unroll
-        for (int p = 0; p < K; ++p)
+        for (int p = 0; p < KK; ++p)
             bxs[p] = (((wk.umask >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::own(box[g0 + p], g0 + p)
                                                                  : Pay<V>::inf();
     }
@@ -93,13 +94,13 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
     __syncthreads();
     BicR before{0, 0, 0}, after{0, 0, 0}, tot{0, 0, 0};
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) {
+    for (int w = 0; w < NW; ++w) {
         const BicR x = sh_bic[w];
         if (w < wid) before = bicr(before, x);
         tot = bicr(tot, x);
     }
 #pragma unroll
-    for (int w = NWAVE - 1; w >= 0; --w)
+    for (int w = NW - 1; w >= 0; --w)
         if (w > wid) after = bicr(sh_bic[w], after);
     pre = bicr(before, pre);
     suf = bicr(suf, after);
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
     {
         int jj = 0;
 #pragma unroll
-        for (int p = 0; p < K; ++p) {
+        for (int p = 0; p < KK; ++p) {
             if ((wk.umask >> p) & 1u) {
                 if (jj < ns) surv |= 1u << p;
                 ++jj;
@@ -126,21 +127,21 @@ __global__ __launch_bounds__(W) void k_reduce(const uint32_t *__restrict__ kind,
     if (BOXES) {
         V agg = Pay<V>::inf();
 #pragma unroll
-        for (int p = 0; p < K; ++p)
+        for (int p = 0; p < KK; ++p)
             if ((surv >> p) & 1u) agg = isect(agg, bxs[p]);
         V wagg;
         cum = wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &wagg);
         if (lane == 0) sh_b[wid] = wagg;
         __syncthreads();
 #pragma unroll
-        for (int w = 0; w < NWAVE - 1; ++w)
+        for (int w = 0; w < NW - 1; ++w)
             if (w < wid) cum = isect(sh_b[w], cum);
     }
 
     const int64_t slot0 = (int64_t)base - baseP;  // first surviving open's slot
     int jj = 0;
 #pragma unroll
-    for (int p = 0; p < K; ++p) {
+    for (int p = 0; p < KK; ++p) {
         if (!((surv >> p) & 1u)) continue;
         const int64_t slot = slot0 + jj;
         ++jj;
@@ -402,8 +403,9 @@ __device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 he
     return R * T + (L - base - 1);
 }
 
-template <bool BOXES, class V>
+template <bool BOXES, class V, int KK>
 struct ResolveSmem {
+    static constexpr int WW = T / KK, NW = WW / WAVE;
     int4 runs[RMAX];
     // Until the walk ends: the clip context at each thread's base level, and
     // the incoming levels [preM, dP] (entry x = level preM + x: the open's
@@ -411,10 +413,10 @@ struct ResolveSmem {
     // over threads.
     union Early {
         struct {
-            V jval[BOXES ? W : 1];
+            V jval[BOXES ? WW : 1];
             int inc_idx[T + 1];
         } w;
-        V ut[BOXES ? 2 * W : 1];
+        V ut[BOXES ? 2 * WW : 1];
     } e;
     // Clip contexts.  Entries [0, aP] belong to the incoming levels; from
     // aP + 1 on come the unmatched opens of each thread in order (thread t's
@@ -425,19 +427,19 @@ struct ResolveSmem {
     V cx[BOXES ? T + 1 : 1];
     // per thread: {lowest level (SENT after a scene start), owner thread or
     // -1, base level, first cx entry | unmatched-open mask << 16 | mask of
-    // those that are clips << 20}; one LDS read per owner-chain hop
-    int4 tinfo[W];
-    static_assert(K <= 4 && T < 0xFFFF, "tinfo packs 4-bit masks and 16-bit entries");
-    int mt[2 * W];
-    int jptr[W];
-    V jval2[BOXES ? W : 1];  // second buffer of the cross-wave pointer jumping
-    int jptr2[W];
-    SegU sh_seg[NWAVE];
-    V wtot[NWAVE];  // union of each wave's leaves
+    // those that are clips << (16 + KK)}; one LDS read per owner-chain hop
+    int4 tinfo[WW];
+    static_assert(KK <= 8 && T < 0xFFFF, "tinfo packs two KK-bit masks above a 16-bit entry");
+    int mt[2 * WW];
+    int jptr[WW];
+    V jval2[BOXES ? WW : 1];  // second buffer of the cross-wave pointer jumping
+    int jptr2[WW];
+    SegU sh_seg[NW];
+    V wtot[NW];  // union of each wave's leaves
 };
 
-template <bool BOXES, class V, class SINK>
-__global__ __launch_bounds__(W) void k_resolve(
+template <bool BOXES, class V, class SINK, int KK>
+__global__ __launch_bounds__(T / KK) void k_resolve(
     const uint32_t *__restrict__ kind, const float4 *__restrict__ box, int64_t n,
     const int64_t *__restrict__ off, int64_t S, const int4 *__restrict__ pinfo,
     const int4 *__restrict__ part, const int4 *__restrict__ runs_g,
@@ -447,7 +449,9 @@ __global__ __launch_bounds__(W) void k_resolve(
     int32_t *__restrict__ cr_c, void *__restrict__ cr_pre, void *__restrict__ ptot,
     int32_t *__restrict__ match, int32_t *__restrict__ pm, SINK sink,
     uint32_t *__restrict__ status) {
-    __shared__ ResolveSmem<BOXES, V> sm;
+    constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
+    static_assert(!BOXES || KK == K, "the box path's unions are built for K elements per thread");
+    __shared__ ResolveSmem<BOXES, V, KK> sm;
     V *ut = sm.e.ut;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
     // Element indices and levels fit in 32 bits (n < 2^31); element indices
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     const uint32_t P = blockIdx.x;
     const uint32_t M = gridDim.x;
     const uint32_t p0 = P * T;
-    const uint32_t g0 = p0 + (uint32_t)t * K;
+    const uint32_t g0 = p0 + (uint32_t)t * KK;
     const uint32_t un = (uint32_t)n;
     const int4 myp = part[P];
     const int dP = myp.x;
@@ -466,28 +470,28 @@ __global__ __launch_bounds__(W) void k_resolve(
     const int rbase = crbase[P];  // this partition's close records start here
 
     // ---- loads: inputs, owner runs
-    uint32_t kr[K], ks[K];
-    load_kinds<K>(kind, n, g0, kr);
-    V bx[K];
+    uint32_t kr[KK], ks[KK];
+    load_kinds<KK>(kind, n, g0, kr);
+    V bx[KK];
     if (BOXES) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) bx[j] = (g0 + j < n) ? Pay<V>::own(box[g0 + j], g0 + j) : Pay<V>::empty();
+        for (int j = 0; j < KK; ++j) bx[j] = (g0 + j < n) ? Pay<V>::own(box[g0 + j], g0 + j) : Pay<V>::empty();
     }
     if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
-    for (int j = 0; j < K; ++j) ks[j] = kr[j] > 4u ? LEAF : kr[j];
-    const uint32_t rm = reset_mask(off, S, g0);
+    for (int j = 0; j < KK; ++j) ks[j] = kr[j] > 4u ? LEAF : kr[j];
+    const uint32_t rm = reset_mask<KK>(off, S, g0);
     __syncthreads();
 
     // ---- gather the incoming levels [preM, dP] (issued now, stored later)
-    constexpr int NG = (T + W) / W;  // entries per thread
+    constexpr int NG = (T + WW) / WW;  // entries per thread
     int g_idx[NG];
     V g_ctx[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
         g_idx[q] = -1;
         g_ctx[q] = Pay<V>::inf();
-        const int x = t + q * W;
+        const int x = t + q * WW;
         const int L = preM + x;
         if (x > aP) continue;
         int64_t R = -1, slot = -1;
@@ -500,10 +504,10 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
 
     // ---- per-thread walk and thread-level depths
-    const Walk wk = walk_kinds<K>(ks, rm);
+    const Walk wk = walk_kinds<KK>(ks, rm);
     const int b = __popc(wk.umask);
     SegU segtot;
-    const SegU ex = block_excl_scan<NWAVE>(SegU{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a, b}, SegUOp{},
+    const SegU ex = block_excl_scan<NW>(SegU{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a, b}, SegUOp{},
                                            SegU{0, 0, 0}, sm.sh_seg, &segtot);
     const int ub = aP + 1 + ex.u;  // this thread's first entry in cx
     const int Dt = ex.r ? ex.v : dP + ex.v;  // absolute depth at thread start
@@ -513,15 +517,15 @@ __global__ __launch_bounds__(W) void k_resolve(
     {
         uint32_t clipm = 0;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < KK; ++j)
             if (ks[j] == BCLIP) clipm |= 1u << j;
-        sm.tinfo[t] = make_int4(cm, -1, base, (int)((uint32_t)ub | (wk.umask << 16) | ((clipm & wk.umask) << 20)));
+        sm.tinfo[t] = make_int4(cm, -1, base, (int)((uint32_t)ub | (wk.umask << 16) | ((clipm & wk.umask) << (16 + KK))));
     }
     if (BOXES) {
         V c = Pay<V>::inf();
         int e = ub;
 #pragma unroll
-        for (int p = 0; p < K; ++p) {
+        for (int p = 0; p < KK; ++p) {
             if ((wk.umask >> p) & 1u) {
                 if (ks[p] == BCLIP) c = isect(c, bx[p]);
                 if (e <= T) sm.cx[e] = c;
@@ -531,31 +535,31 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
-        const int x = t + q * W;
+        const int x = t + q * WW;
         if (x > aP) continue;
         sm.e.w.inc_idx[x] = g_idx[q];
         if (BOXES) sm.cx[x] = g_ctx[q];
     }
     int wmin0;
     int premin = wave_excl_scan(cm, MinOp{}, INT32_MAX, &wmin0);  // lowest level of earlier lanes
-    mintree_build(sm.mt, cm);  // its barrier also publishes everything above
+    mintree_build<WW>(sm.mt, cm);  // its barrier also publishes everything above
 
     // levels at or below `lowtop` are held by no earlier thread of this
     // partition: they come from earlier partitions (the LDS table).
 #pragma unroll
-    for (int w = 0; w < NWAVE - 1; ++w)
-        if (w < (t >> 6)) premin = min(premin, sm.mt[NWAVE + w]);  // wave nodes of the min tree
+    for (int w = 0; w < NW - 1; ++w)
+        if (w < (t >> 6)) premin = min(premin, sm.mt[NW + w]);  // wave nodes of the min tree
     const int lowtop = min(premin, Dt);
     // lowest level any later thread reaches: an unmatched open of this thread
     // at a level not above it survives the partition
     int wmin1;
     int sufmin = wave_excl_suffix_scan(cm, MinOp{}, INT32_MAX, &wmin1);
 #pragma unroll
-    for (int w = 1; w < NWAVE; ++w)
-        if (w > (t >> 6)) sufmin = min(sufmin, sm.mt[NWAVE + w]);
+    for (int w = 1; w < NW; ++w)
+        if (w > (t >> 6)) sufmin = min(sufmin, sm.mt[NW + w]);
     // owner links between threads: the entry just below a thread's lowest
     // level belongs to the nearest earlier thread with a smaller lowest level
-    const int tl = wk.rs ? -1 : mintree_prev_less(sm.mt, t, cm);
+    const int tl = wk.rs ? -1 : mintree_prev_less<WW>(sm.mt, t, cm);
     sm.tinfo[t].y = tl;
 
     // ---- clip context at each thread's base level: pointer jumping along
@@ -568,7 +572,7 @@ __global__ __launch_bounds__(W) void k_resolve(
             if (s >= 0) {
                 const int4 ti = sm.tinfo[s];
                 const int jj = pre_m - ti.z - 1;
-                const uint32_t um = ((uint32_t)ti.w >> 16) & 0xFu;
+                const uint32_t um = ((uint32_t)ti.w >> 16) & ((1u << KK) - 1u);
                 const int e = (ti.w & 0xFFFF) + (int)jj;
                 if (jj >= 0 && jj < __popc(um) && e <= T) {
                     v = sm.cx[e];
@@ -591,7 +595,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
         // Across waves every pointer now leaves its wave, so two doubling
         // rounds (double-buffered) reach the partition's base for 4 waves.
-        static_assert(NWAVE <= 4, "two doubling rounds cover at most four waves");
+        static_assert(NW <= 4, "two doubling rounds cover at most four waves");
         sm.e.w.jval[t] = v;
         sm.jptr[t] = ptr;
         __syncthreads();  // also publishes tlink
@@ -622,16 +626,16 @@ __global__ __launch_bounds__(W) void k_resolve(
     uint32_t mkeep = 0;   // match rows this thread writes at the end
     uint32_t lbm = 0;     // closes of blends opened in this thread
     uint32_t defmask = 0; // closes of blends opened before this thread
-    uint32_t errs = 0;    // status bits, 4 per element; element g0 - 1 at bit 4K
+    uint64_t errs = 0;    // status bits, 4 per element; element g0 - 1 at bit 4KK
     bool rseen = false;
     int dep = Dt;
-    V octx[K], res[K];
-    int mv[K];
-    uint32_t lbp = 0;  // 2 bits per position: the local open a blend close matches
+    V octx[KK], res[KK];
+    int mv[KK];
+    uint32_t lbp = 0;  // 3 bits per position: the local open a blend close matches
     // per deferred blend close, packed: owner thread + 1 (0 = an earlier
     // partition), its position and cx entry; or, for an earlier partition,
     // the close record's index within this partition
-    uint32_t dfw[K];
+    uint32_t dfw[KK];
     // the stack entry at level `cur_L` seen from this thread's start; the
     // levels asked for only decrease, so the owner search moves left along
     // owner links from the previous thread
@@ -640,19 +644,19 @@ __global__ __launch_bounds__(W) void k_resolve(
     int cur_kind = -1, cur_own = -1, cur_pos = -1, cur_ent = -1;
     V cur_ctx = Pay<V>::inf();
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < KK; ++j) {
         octx[j] = Pay<V>::inf();
         res[j] = Pay<V>::empty();
         mv[j] = -1;
         dfw[j] = 0;
     }
 #pragma clang loop unroll(full)
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < KK; ++j) {
         const uint32_t i = g0 + j;
         const bool real = i < un;
         const uint32_t bit = 1u << j;
         if ((rm >> j) & 1u) {
-            if (real && i > 0 && dep != 0) errs |= ST_UNBAL << (j > 0 ? 4 * (j - 1) : 4 * K);  // element i - 1
+            if (real && i > 0 && dep != 0) errs |= (uint64_t)ST_UNBAL << (j > 0 ? 4 * (j - 1) : 4 * KK);  // element i - 1
             mask = 0;
             rseen = true;
             dep = 0;
@@ -661,7 +665,7 @@ __global__ __launch_bounds__(W) void k_resolve(
                 soff = (int)off[sid];
             }
         }
-        if (real && kr[j] > 4u) errs |= ST_BAD_KIND << (4 * j);
+        if (real && kr[j] > 4u) errs |= (uint64_t)ST_BAD_KIND << (4 * j);
         const int tp = mask ? msb32(mask) : -1;
         if (tp < 0 && !rseen && cur_L != dep) {
             cur_L = dep;
@@ -689,13 +693,13 @@ __global__ __launch_bounds__(W) void k_resolve(
                 const int s = own_s;
                 if (s >= 0) {
                     const int jj = dep - ti.z - 1;
-                    const uint32_t um = ((uint32_t)ti.w >> 16) & 0xFu;
+                    const uint32_t um = ((uint32_t)ti.w >> 16) & ((1u << KK) - 1u);
                     const int e = (ti.w & 0xFFFF) + (int)jj;
                     if (jj >= 0 && jj < __popc(um) && e <= T) {
-                        const int p = nth_bit(um, (int)jj);
-                        cur_idx = (int)(p0 + (uint32_t)s * K + p);
+                        const int p = nth_bit<KK>(um, (int)jj);
+                        cur_idx = (int)(p0 + (uint32_t)s * KK + p);
                         if (BOXES) cur_ctx = isect(sm.e.w.jval[s], sm.cx[e]);
-                        cur_kind = (((uint32_t)ti.w >> (20 + p)) & 1u) ? (int)BCLIP : (int)BBLEND;
+                        cur_kind = (((uint32_t)ti.w >> (16 + KK + p)) & 1u) ? (int)BCLIP : (int)BBLEND;
                         cur_own = s;
                         cur_pos = p;
                         cur_ent = e;
@@ -742,14 +746,14 @@ __global__ __launch_bounds__(W) void k_resolve(
         }
         const bool mism = (lclose && ((k == ECLIP) != (((clipm >> tps) & 1u) != 0))) ||
                           (rok && ((k == ECLIP) != (cur_kind == (int)BCLIP)));
-        errs |= (real && mism) ? ST_MISMATCH << (4 * j) : 0u;
-        errs |= (real && (rootclose || (rclose && !rok))) ? ST_UNBAL << (4 * j) : 0u;
+        errs |= (real && mism) ? (uint64_t)ST_MISMATCH << (4 * j) : 0u;
+        errs |= (real && (rootclose || (rclose && !rok))) ? (uint64_t)ST_UNBAL << (4 * j) : 0u;
         leafm |= isleaf ? bit : 0u;
         clipm |= k == BCLIP ? bit : 0u;
         keep |= (isleaf || (k == BCLIP && !sclip) || (k == ECLIP && (lclose || (rok && !rec)))) ? bit : 0u;
         keep |= (lclose && k == EBLEND) ? (bit | pbit) : 0u;
         lbm |= (lclose && k == EBLEND) ? bit : 0u;
-        lbp |= (uint32_t)tps << (2 * j);
+        lbp |= (uint32_t)tps << (3 * j);
         mkeep |= (isleaf || lclose || (rok && !rec)) ? bit : 0u;
         mkeep |= pbit;
         mv[j] = lclose ? (int32_t)(g0 + tps - soff) : rok ? (int32_t)(cur_idx - soff) : -1;
@@ -759,8 +763,8 @@ __global__ __launch_bounds__(W) void k_resolve(
         if (rok && !rec && match && real && (uint32_t)cur_idx < un) match[cur_idx] = (int32_t)(i - soff);
         if (BOXES && rok && k == EBLEND && real) {
             defmask |= bit;
-            dfw[j] = cur_own >= 0 ? (uint32_t)(cur_own + 1) | ((uint32_t)cur_pos << 9) | ((uint32_t)cur_ent << 11)
-                                  : (uint32_t)(dP - dep) << 11;
+            dfw[j] = cur_own >= 0 ? (uint32_t)(cur_own + 1) | ((uint32_t)cur_pos << 9) | ((uint32_t)cur_ent << 12)
+                                  : (uint32_t)(dP - dep) << 12;
         }
         // the close's position, with the top bit set for a blend; the slot was
         // written by the gather
@@ -770,17 +774,17 @@ __global__ __launch_bounds__(W) void k_resolve(
     }
     if (errs) {  // malformed input only: raise each element's bits in its scene's word
 #pragma unroll
-        for (int j = 0; j <= K; ++j) {
-            const uint32_t bj = (errs >> (4 * j)) & 0xFu;
-            if (bj) flag(status, off, S, j < K ? (int64_t)g0 + j : (int64_t)g0 - 1, bj);
+        for (int j = 0; j <= KK; ++j) {
+            const uint32_t bj = (uint32_t)(errs >> (4 * j)) & 0xFu;
+            if (bj) flag(status, off, S, j < KK ? (int64_t)g0 + j : (int64_t)g0 - 1, bj);
         }
     }
     // blends opened and closed in this thread: the union of the leaves between
     if (BOXES) {
 #pragma unroll
-        for (int j = 1; j < K; ++j) {
+        for (int j = 1; j < KK; ++j) {
             if (!((lbm >> j) & 1u)) continue;
-            const int p = (lbp >> (2 * j)) & 3u;
+            const int p = (lbp >> (3 * j)) & 7u;
             V u = Pay<V>::empty();
 #pragma unroll
             for (int q = 1; q < j; ++q)
@@ -791,12 +795,12 @@ __global__ __launch_bounds__(W) void k_resolve(
                 if (q == p) res[q] = u;
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < KK; ++j)
             if (((keep >> j) & 1u) && g0 + j < un) sink.emit(g0 + j, res[j]);
     }
     if (match) {
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < KK; ++j)
             if (((mkeep >> j) & 1u) && g0 + j < un) match[g0 + j] = mv[j];
     }
     if (!BOXES) return;
@@ -807,7 +811,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     // an arbitrary range, answered from a union tree over threads.
     V ttot = Pay<V>::empty();
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+    for (int j = 0; j < KK; ++j)
         if ((leafm >> j) & 1u) ttot = unite(ttot, res[j]);
     const int wid = t >> 6;
     V wtot_u;
@@ -821,7 +825,7 @@ __global__ __launch_bounds__(W) void k_resolve(
         V suf = Pay<V>::empty();
         int e = ub + __popc(wk.umask);
 #pragma unroll
-        for (int p = K - 1; p >= 0; --p) {
+        for (int p = KK - 1; p >= 0; --p) {
             if ((wk.umask >> p) & 1u) {
                 --e;
                 if (e <= T) sm.cx[e] = suf;
@@ -832,7 +836,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     __syncthreads();
     V pre_t = wpre, suf_t = wsuf, all = Pay<V>::empty();
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) {
+    for (int w = 0; w < NW; ++w) {
         const V x = sm.wtot[w];
         if (w < wid) pre_t = unite(pre_t, x);
         if (w > wid) suf_t = unite(suf_t, x);
@@ -841,7 +845,7 @@ __global__ __launch_bounds__(W) void k_resolve(
     // closes of blends opened in an earlier partition: the prefix part
     uint32_t dloc = 0;  // closes of blends opened in an earlier thread of this partition
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < KK; ++j) {
         if (!((defmask >> j) & 1u)) continue;
         if (dfw[j] & 0x1FFu) {  // owner thread in this partition
             dloc |= 1u << j;
@@ -851,34 +855,34 @@ __global__ __launch_bounds__(W) void k_resolve(
 #pragma unroll
         for (int q = 0; q < j; ++q)
             if ((leafm >> q) & 1u) pre = unite(pre, res[q]);
-        const int ci = (int)(dfw[j] >> 11);
+        const int ci = (int)(dfw[j] >> 12);
         if (ci < aP && (uint32_t)(rbase + ci) < un)
             Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
     }
     // closes of blends opened in an earlier thread of this partition, taken
     // one per round so a wave runs as many rounds as its busiest lane needs
-    for (int it = 0; it < K && __ballot(dloc != 0); ++it) {
+    for (int it = 0; it < KK && __ballot(dloc != 0); ++it) {
         if (!dloc) continue;
         const int j = __builtin_ctz(dloc);
         dloc &= dloc - 1;
         uint32_t w = 0;
         V pre = Pay<V>::empty();
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
+        for (int q = 0; q < KK; ++q) {
             if (q == j) w = dfw[q];
             if (q < j && ((leafm >> q) & 1u)) pre = unite(pre, res[q]);
         }
-        const int s = (int)(w & 0x1FFu) - 1, pos = (int)((w >> 9) & 3u), ent = (int)(w >> 11);
+        const int s = (int)(w & 0x1FFu) - 1, pos = (int)((w >> 9) & 7u), ent = (int)(w >> 12);
         const V u = unite(unite(sm.cx[ent], uniontree_inner(ut, s + 1, t - 1)), pre);
         sink.emit(g0 + j, u);
-        sink.emit(p0 + (uint32_t)s * K + pos, u);
+        sink.emit(p0 + (uint32_t)s * KK + pos, u);
     }
     // surviving blend opens: union from the open to the end of the partition
     {
         const int baseP = myp.z;
         int jj = 0;
 #pragma unroll
-        for (int p = 0; p < K; ++p) {
+        for (int p = 0; p < KK; ++p) {
             if (!((wk.umask >> p) & 1u)) continue;
             const int L = base + 1 + jj;
             const int e = ub + jj;
@@ -1170,7 +1174,8 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     int *crtot = (int *)(w + L.crtot);
     int32_t *U_idx = (int32_t *)(w + L.U_idx);
     void *U_cum = w + L.U_cum;
-    k_reduce<BOXES, V><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
+    constexpr int KD = BOXES ? K : 8;  // elements per thread of the reduce
+    k_reduce<BOXES, V, KD><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
@@ -1203,7 +1208,10 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     void *ptot = w + L.ptot;
     const bool prof = g_prof_before && g_prof_after;
     if (prof) (void)hipEventRecord(g_prof_before, st);
-    k_resolve<BOXES, V, SINK><<<(unsigned)M, W, 0, st>>>(kind, box, n, off, S, pinfo, part, runs,
+    // matching alone needs few registers: 8 elements per thread halves the
+    // per-thread work of the partition-level steps
+    constexpr int KR = BOXES ? K : 8;
+    k_resolve<BOXES, V, SINK, KR><<<(unsigned)M, T / KR, 0, st>>>(kind, box, n, off, S, pinfo, part, runs,
                                                          rhead, jv[cur], U_idx, U_cum, U_suf,
                                                          crbase, cr_slot, cr_c, cr_pre, ptot, match,
                                                          pm, sink, status);

@@ -142,3 +142,30 @@ def test_batched_unbalanced_scene_on_partition_boundary():
              chain(500, rng)]
     kind, box, off = scenes_to_batch(parts)
     check_batched(kind, box, off, "unbalanced scenes", bad=(0, 2))
+
+
+@pytest.mark.parametrize("depth", [T // 2, T, 3 * T + 2])
+def test_match_only_chains(depth):
+    """The matching-only path (its own thread layout) on chains crossing
+    partition boundaries."""
+    rng = np.random.default_rng(depth)
+    k, _ = chain(depth, rng, leaves_mid=5)
+    k = np.concatenate([gen.walk(777, 9, 31)[0], k, gen.walk(1001, 40, 32)[0]]).astype(np.uint32)
+    say(f"[edge] match chain {depth} n={len(k)}")
+    m, pm, st = gpu_match(k)
+    om, opm, ost = oracle.match(k)
+    assert st == 0 and ost == 0
+    assert np.array_equal(m, om) and np.array_equal(pm, opm)
+
+
+def test_match_only_status_bits():
+    k, _ = gen.walk(5000, 30, 1)
+    closes = np.nonzero(k == 2)[0]
+    k1 = k.copy(); k1[2500] = 9
+    k2 = np.concatenate([k, [2]]).astype(np.uint32)
+    k3 = np.concatenate([[1], k]).astype(np.uint32)
+    k4 = k.copy(); k4[closes[len(closes) // 2]] = 4
+    for kk in (k1, k2, k3, k4):
+        _, _, ost = oracle.match(kk)
+        _, _, st = gpu_match(kk)
+        assert ost != 0 and st == ost, (ost, st)
