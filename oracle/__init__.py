@@ -38,7 +38,9 @@ def lib():
         L.tbo_bbox_f64.argtypes = [P, P, I64, P]
         L.tbo_backward.argtypes = [P, P, P, I64, P]
         L.tbo_sources.argtypes = [P, P, I64, P]
-        for f in (L.tbo_bbox, L.tbo_match, L.tbo_bbox_f64, L.tbo_backward, L.tbo_sources):
+        L.tbo_compose.argtypes = [P, P, I64, P]
+        for f in (L.tbo_bbox, L.tbo_match, L.tbo_bbox_f64, L.tbo_backward, L.tbo_sources,
+                  L.tbo_compose):
             f.restype = U32
         _lib = L
     return _lib
@@ -97,3 +99,14 @@ def sources(kind, box):
     src = np.empty((n, 4), np.int64)
     st = lib().tbo_sources(kind.ctypes.data, box.ctypes.data, n, src.ctypes.data)
     return src, int(st)
+
+
+def compose(kind, xf):
+    """Transform composition down the tree: xf uint32[n,6] rows [a b c d e f]
+    (mod 2^32).  Returns (out uint32[n,6], status)."""
+    kind = _c(kind, np.uint32)
+    xf = _c(xf, np.uint32).reshape(-1, 6)
+    n = kind.shape[0]
+    out = np.empty((n, 6), np.uint32)
+    st = lib().tbo_compose(kind.ctypes.data, xf.ctypes.data, n, out.ctypes.data)
+    return out, int(st)

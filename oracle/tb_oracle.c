@@ -324,3 +324,61 @@ uint32_t tbo_backward(const uint32_t *kind, const float *box, const float *grad_
     free(src), free(acc);
     return status;
 }
+
+/*
+ * Composition of a transform monoid down the tree (the Introduction names
+ * transforms composed down a skeleton as an application of the same method
+ * to a general monoid).  Every open carries a 2-D affine transform
+ * [a b c; d e f] on integer coordinates, arithmetic modulo 2^32 (exact, so
+ * associative, and not commutative).  Element i's output is the product of
+ * the transforms of all opens enclosing it, outermost first; an open's
+ * output includes its own transform, and a close's output is its open's.
+ * Leaves' and closes' input rows are ignored.  Both open kinds carry a
+ * transform and closes pop either kind (kind pairs are not checked).
+ * Walk: the stack of Fig. 1, each entry holding the product down to it.
+ */
+typedef struct { uint32_t a, b, c, d, e, f; } aff;
+
+static aff aff_id(void) { aff r = {1u, 0u, 0u, 0u, 1u, 0u}; return r; }
+/* p . q : apply q first, then p */
+static aff aff_mul(aff p, aff q) {
+    aff r;
+    r.a = p.a * q.a + p.b * q.d;
+    r.b = p.a * q.b + p.b * q.e;
+    r.c = p.a * q.c + p.b * q.f + p.c;
+    r.d = p.d * q.a + p.e * q.d;
+    r.e = p.d * q.b + p.e * q.e;
+    r.f = p.d * q.c + p.e * q.f + p.f;
+    return r;
+}
+
+uint32_t tbo_compose(const uint32_t *kind, const uint32_t *xf, int64_t n, uint32_t *out) {
+    uint32_t status = 0;
+    aff *S = (aff *)malloc(sizeof(aff) * (size_t)(n + 1));
+    if (!S) return 0x80000000u;
+    int64_t sp = 0;
+    S[sp++] = aff_id(); /* the root: nothing applied */
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t k = kind[i];
+        aff o = S[sp - 1];
+        if (k > END_BLEND) {
+            status |= ST_BAD_KIND;
+        } else if (k == BEGIN_CLIP || k == BEGIN_BLEND) {
+            const uint32_t *x = xf + 6 * i;
+            aff own = {x[0], x[1], x[2], x[3], x[4], x[5]};
+            o = aff_mul(S[sp - 1], own);
+            S[sp++] = o;
+        } else if (k == END_CLIP || k == END_BLEND) {
+            if (sp == 1) {
+                status |= ST_UNBALANCED;
+            } else {
+                o = S[--sp];
+            }
+        }
+        uint32_t *y = out + 6 * i;
+        y[0] = o.a, y[1] = o.b, y[2] = o.c, y[3] = o.d, y[4] = o.e, y[5] = o.f;
+    }
+    if (sp != 1) status |= ST_UNBALANCED;
+    free(S);
+    return status;
+}

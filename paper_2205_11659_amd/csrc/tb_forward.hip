@@ -319,7 +319,7 @@ __global__ void k_jump(const int32_t *__restrict__ ptr_in, const void *__restric
     int32_t p = ptr_in[P];
     V v = Pay<V>::ld(val_in, P);
     if (p >= 0) {
-        v = isect(v, Pay<V>::ld(val_in, p));
+        v = isect(Pay<V>::ld(val_in, p), v);  // ancestor first
         p = ptr_in[p];
     }
     ptr_out[P] = p;
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
         if (BOXES && x >= 1 && (uint32_t)(rbase + aP - x) < un) cr_slot[rbase + aP - x] = (int32_t)slot;
         if (slot < 0) continue;
         g_idx[q] = U_idx[slot];
-        if (BOXES) g_ctx[q] = isect(Pay<V>::ld(U_cum, slot), Pay<V>::ld(base_ctx, R));
+        if (BOXES) g_ctx[q] = isect(Pay<V>::ld(base_ctx, R), Pay<V>::ld(U_cum, slot));
     }
 
     // ---- per-thread walk and thread-level depths
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
             const V vv = shfl_idx(v, src);
             const int pp = __shfl(ptr, src, WAVE);
             if (in) {
-                v = isect(v, vv);
+                v = isect(vv, v);  // the owner's context comes first
                 ptr = pp;
             }
         }
@@ -600,13 +600,13 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
         sm.jptr[t] = ptr;
         __syncthreads();  // also publishes tlink
         if (ptr >= 0) {
-            v = isect(v, sm.e.w.jval[ptr]);
+            v = isect(sm.e.w.jval[ptr], v);
             ptr = sm.jptr[ptr];
         }
         sm.jval2[t] = v;
         sm.jptr2[t] = ptr;
         __syncthreads();
-        if (ptr >= 0) v = isect(v, sm.jval2[ptr]);
+        if (ptr >= 0) v = isect(sm.jval2[ptr], v);
         sm.e.w.jval[t] = v;  // every read of the first buffer happened before the barrier
         __syncthreads();
     } else {
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
         const int tps = tp < 0 ? 0 : tp;
         const uint32_t pbit = lclose ? (1u << tps) : 0u;
         if (BOXES) {
-            const V ix = isect(bx[j], ctx);
+            const V ix = isect(ctx, bx[j]);
             octx[j] = k == BCLIP ? ix : ctx;
             // leaf: its clipped box; BEGIN_CLIP: likewise; END_CLIP: the
             // context inside its open.  Blend rows are filled in later.
@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
             ui[q] = U_idx[s0];
             // only the loads this kind of pair uses (the others read entry 0)
             const int64_t sc = bl[q] ? 0 : s0, sb = bl[q] ? s0 : 0;
-            cl[q] = isect(Pay<V>::ld(U_cum, sc), Pay<V>::ld(base_ctx, sc / T));
+            cl[q] = isect(Pay<V>::ld(base_ctx, sc / T), Pay<V>::ld(U_cum, sc));
             part[q] = unite(Pay<V>::ld(U_suf, sb), Pay<V>::ld(cr_pre, ok[q] && bl[q] ? r : 0));
             // whole partitions strictly between: [a, b]
             const int64_t a = ok[q] && bl[q] ? sl[q] / T + 1 : 1, b = ok[q] && bl[q] ? cc[q] / T - 1 : 0;
