@@ -70,6 +70,12 @@ typedef struct {
     float x0, y0, x1, y1;
 } tb_box;
 
+/* 2-D affine transform [a b c; d e f] on integer coordinates (x, y) ->
+   (a x + b y + c, d x + e y + f), arithmetic modulo 2^32.  24 bytes. */
+typedef struct {
+    uint32_t a, b, c, d, e, f;
+} tb_affine;
+
 typedef enum {
     TB_OK = 0,
     TB_ERR_NULL = 1,      /* a required pointer is NULL */
@@ -91,6 +97,7 @@ typedef enum {
 #define TB_OP_BBOX 1
 #define TB_OP_BBOX_BACKWARD 2
 #define TB_OP_BBOX_BATCHED 3
+#define TB_OP_COMPOSE 4
 
 /* Workspace bytes needed by `op` for n elements (num_scenes is used by
    TB_OP_BBOX_BATCHED only; pass 1 otherwise).  Returns 0 for invalid sizes. */
@@ -155,6 +162,24 @@ tb_status tb_bbox_backward(const uint32_t *kind, const tb_box *box_in, const tb_
 tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int64_t *offsets,
                           int64_t num_scenes, int64_t total_n, int32_t *match, tb_box *box_out,
                           void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
+ * Composition of transforms down the tree: the same method applied to a
+ * general, non-commutative monoid (the Introduction names transforms composed
+ * down a skeleton as such an application).  Every open element, of either
+ * kind, carries a transform; element i's output is the product of the
+ * transforms of all opens enclosing it, outermost first (p.q applies q
+ * first), including its own if it is an open; a close's output is its open's.
+ * Arithmetic modulo 2^32 is exact and associative, so the result is the
+ * sequential walk's bit for bit however the parallel steps group products.
+ *   kind   [n]  uint32 tb_kind values; kind pairs are not checked   (in)
+ *   xf_in  [n]  tb_affine, rows of opens used, 8-byte aligned        (in)
+ *   xf_out [n]  tb_affine composed transform per element, 8-byte aligned (out)
+ *   dev_status [1] uint32: TB_DATA_BAD_KIND, TB_DATA_UNBALANCED       (out)
+ * Workspace: tb_workspace_bytes(TB_OP_COMPOSE, n, 1).
+ */
+tb_status tb_compose(const uint32_t *kind, const tb_affine *xf_in, int64_t n, tb_affine *xf_out,
+                     void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream);
 
 /*
  * Profiling hook: when both are non-NULL, later calls record `before` and

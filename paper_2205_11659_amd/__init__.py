@@ -21,7 +21,7 @@ from ._build import LIB, build  # noqa: F401
 
 LEAF, BEGIN_CLIP, END_CLIP, BEGIN_BLEND, END_BLEND = range(5)
 DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS = 1, 2, 4, 8
-OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED = range(4)
+OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE = range(5)
 
 _lib = None
 
@@ -44,7 +44,8 @@ def lib():
         L.tb_bbox.argtypes = [P, P, I64, P, P, P, SZ, P, P]
         L.tb_bbox_backward.argtypes = [P, P, P, I64, P, P, SZ, P, P]
         L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
-        for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched):
+        L.tb_compose.argtypes = [P, P, I64, P, P, SZ, P, P]
+        for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched, L.tb_compose):
             f.restype = ctypes.c_int
         L.tb_status_str.argtypes = [ctypes.c_int]
         L.tb_status_str.restype = ctypes.c_char_p
@@ -168,6 +169,24 @@ def tb_bbox_backward(kind, box, grad_out):
     _check(lib().tb_bbox_backward(_ptr(kind), _ptr(box), _ptr(grad_out), n, _ptr(gin),
                                   ctypes.c_void_p(ws), wsb, _ptr(status), _stream()))
     return gin, status
+
+
+def tb_compose(kind, xf, out=None, status=None):
+    """Transforms composed down the tree.  `xf` holds int32[n, 6] rows
+    [a b c d e f] read as uint32 modulo 2^32 (rows of opens are used).
+    Returns (out int32[n, 6], status int32[1])."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    if xf.dtype != torch.int32 or xf.shape != (n, 6):
+        raise TypeError("xf must be int32 [n, 6]")
+    xf = xf.contiguous()
+    dev = kind.device
+    out = torch.empty((n, 6), dtype=torch.int32, device=dev) if out is None else out
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    ws, wsb = workspace(OP_COMPOSE, n, 1, dev)
+    _check(lib().tb_compose(_ptr(kind), _ptr(xf), n, _ptr(out), ctypes.c_void_p(ws), wsb,
+                            _ptr(status), _stream()))
+    return out, status
 
 
 class TreeBBoxFn(torch.autograd.Function):

@@ -87,7 +87,13 @@ template <>
 struct Pay<Box> {
     static __device__ __forceinline__ Box inf() { return box_inf(); }
     static __device__ __forceinline__ Box empty() { return box_empty(); }
+    static constexpr bool kUnions = true;     // blend unions up the tree
+    static constexpr bool kLeafOwn = true;    // a leaf's row combines its own input
+    static constexpr bool kAllOpens = false;  // both open kinds carry a payload
     static __device__ __forceinline__ Box own(float4 b, int64_t) { return {b.x, b.y, b.z, b.w}; }
+    static __device__ __forceinline__ Box in(const void *base, int64_t i) {
+        return own(((const float4 *)base)[i], i);
+    }
     static __device__ __forceinline__ Box ld(const void *base, int64_t i) {
         return ld_box((const float4 *)base, i);
     }
@@ -104,6 +110,12 @@ struct Pay<BoxS> {
     static __device__ __forceinline__ BoxS empty() {
         return {INFINITY, INFINITY, -INFINITY, -INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
     }
+    static constexpr bool kUnions = true;
+    static constexpr bool kLeafOwn = true;
+    static constexpr bool kAllOpens = false;
+    static __device__ __forceinline__ BoxS in(const void *base, int64_t i) {
+        return own(((const float4 *)base)[i], i);
+    }
     static __device__ __forceinline__ BoxS own(float4 b, int64_t i) {
         const int32_t s = (int32_t)i;
         return {b.x, b.y, b.z, b.w, s, s, s, s};
@@ -118,6 +130,44 @@ struct Pay<BoxS> {
         ((int4 *)base)[2 * i + 1] = make_int4(v.s0, v.s1, v.s2, v.s3);
     }
     static __device__ __forceinline__ bool nonempty(const BoxS &v) { return v.x0 < v.x1 && v.y0 < v.y1; }
+};
+
+// A 2-D affine transform [a b c; d e f] on integer coordinates, arithmetic
+// modulo 2^32: exact, hence associative, and not commutative.  As a payload
+// composed down the tree, "isect(p, q)" is p . q (q applied first): the
+// enclosing transform p always comes first at every combine.
+struct Aff {
+    uint32_t a, b, c, d, e, f;
+};
+__device__ __forceinline__ Aff aff_id() { return {1u, 0u, 0u, 0u, 1u, 0u}; }
+__device__ __forceinline__ Aff isect(const Aff &p, const Aff &q) {
+    return {p.a * q.a + p.b * q.d, p.a * q.b + p.b * q.e, p.a * q.c + p.b * q.f + p.c,
+            p.d * q.a + p.e * q.d, p.d * q.b + p.e * q.e, p.d * q.c + p.e * q.f + p.f};
+}
+// there is nothing to combine upwards; the union steps are compiled out
+__device__ __forceinline__ Aff unite(Aff a, const Aff &) { return a; }
+__device__ __forceinline__ Aff canon(Aff a) { return a; }
+template <>
+struct Pay<Aff> {
+    static constexpr bool kUnions = false;
+    static constexpr bool kLeafOwn = false;
+    static constexpr bool kAllOpens = true;
+    static __device__ __forceinline__ Aff inf() { return aff_id(); }
+    static __device__ __forceinline__ Aff empty() { return aff_id(); }
+    // rows of 24 bytes, 8-byte aligned
+    static __device__ __forceinline__ Aff ld(const void *base, int64_t i) {
+        const uint2 *q = (const uint2 *)base + 3 * i;
+        const uint2 x = q[0], y = q[1], z = q[2];
+        return {x.x, x.y, y.x, y.y, z.x, z.y};
+    }
+    static __device__ __forceinline__ Aff in(const void *base, int64_t i) { return ld(base, i); }
+    static __device__ __forceinline__ void st(void *base, int64_t i, const Aff &v) {
+        uint2 *q = (uint2 *)base + 3 * i;
+        q[0] = make_uint2(v.a, v.b);
+        q[1] = make_uint2(v.c, v.d);
+        q[2] = make_uint2(v.e, v.f);
+    }
+    static __device__ __forceinline__ bool nonempty(const Aff &) { return true; }
 };
 
 // ---------------------------------------------------------- wave shuffles
@@ -160,6 +210,21 @@ __device__ __forceinline__ BoxS rdlane(BoxS v, int l) {
             rdlane(v.s0, l), rdlane(v.s1, l), rdlane(v.s2, l), rdlane(v.s3, l)};
 }
 
+template <int C, int RM = 0xF>
+__device__ __forceinline__ Aff dmov(Aff o, Aff v) {
+    return {(uint32_t)dmov<C, RM>((int)o.a, (int)v.a), (uint32_t)dmov<C, RM>((int)o.b, (int)v.b),
+            (uint32_t)dmov<C, RM>((int)o.c, (int)v.c), (uint32_t)dmov<C, RM>((int)o.d, (int)v.d),
+            (uint32_t)dmov<C, RM>((int)o.e, (int)v.e), (uint32_t)dmov<C, RM>((int)o.f, (int)v.f)};
+}
+__device__ __forceinline__ Aff rdlane(Aff v, int l) {
+    return {(uint32_t)rdlane((int)v.a, l), (uint32_t)rdlane((int)v.b, l), (uint32_t)rdlane((int)v.c, l),
+            (uint32_t)rdlane((int)v.d, l), (uint32_t)rdlane((int)v.e, l), (uint32_t)rdlane((int)v.f, l)};
+}
+__device__ __forceinline__ Aff shfl_idx(Aff v, int src) {
+    return {(uint32_t)__shfl((int)v.a, src, WAVE), (uint32_t)__shfl((int)v.b, src, WAVE),
+            (uint32_t)__shfl((int)v.c, src, WAVE), (uint32_t)__shfl((int)v.d, src, WAVE),
+            (uint32_t)__shfl((int)v.e, src, WAVE), (uint32_t)__shfl((int)v.f, src, WAVE)};
+}
 // arbitrary-lane reads
 __device__ __forceinline__ Box shfl_idx(Box v, int src) {
     return {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE), __shfl(v.y1, src, WAVE)};
@@ -292,6 +357,12 @@ __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *tota
     *total = tot;
     __syncthreads();
     return op(pre, ex);
+}
+
+// both open kinds as BEGIN_CLIP and both closes as END_CLIP (payloads that
+// every open carries)
+__device__ __forceinline__ uint32_t as_clip(uint32_t k) {
+    return k == BBLEND ? (uint32_t)BCLIP : k == EBLEND ? (uint32_t)ECLIP : k;
 }
 
 // ----------------------------------------------------------- small helpers

@@ -28,6 +28,10 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
                    void *ws, uint32_t *status, hipStream_t st);
 
 // Enqueue the gradient pass (recompute with attaining indices + exact sums).
+// Transform composition down the tree: xf and out hold 24-byte rows
+// [a b c d e f] (uint32, 8-byte aligned).
+hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,
+                       uint32_t *status, hipStream_t st);
 hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,
                    float4 *grad_in, void *ws, uint32_t *status, hipStream_t st);
 

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     load_kinds<KK>(kind, n, g0, ks);
 #pragma unroll
     for (int j = 0; j < KK; ++j)
-        if (ks[j] > 4u) ks[j] = LEAF;
+        ks[j] = ks[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(ks[j]) : ks[j];
     const uint32_t rm = reset_mask<KK>(off, S, g0);
     const Walk wk = walk_kinds<KK>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     if (BOXES) {
 #pragma unroll
         for (int p = 0; p < KK; ++p)
-            bxs[p] = (((wk.umask >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::own(box[g0 + p], g0 + p)
+            bxs[p] = (((wk.umask >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::in(box, g0 + p)
                                                                  : Pay<V>::inf();
     }
 
@@ -133,8 +133,10 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
         cum = wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &wagg);
         if (lane == 0) sh_b[wid] = wagg;
         __syncthreads();
+        // earlier waves' products go in front, nearest wave first (the
+        // combine need not be commutative)
 #pragma unroll
-        for (int w = 0; w < NW - 1; ++w)
+        for (int w = NW - 2; w >= 0; --w)
             if (w < wid) cum = isect(sh_b[w], cum);
     }
 
@@ -475,11 +477,11 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     V bx[KK];
     if (BOXES) {
 #pragma unroll
-        for (int j = 0; j < KK; ++j) bx[j] = (g0 + j < n) ? Pay<V>::own(box[g0 + j], g0 + j) : Pay<V>::empty();
+        for (int j = 0; j < KK; ++j) bx[j] = (g0 + j < n) ? Pay<V>::in(box, g0 + j) : Pay<V>::empty();
     }
     if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
-    for (int j = 0; j < KK; ++j) ks[j] = kr[j] > 4u ? LEAF : kr[j];
+    for (int j = 0; j < KK; ++j) ks[j] = kr[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(kr[j]) : kr[j];
     const uint32_t rm = reset_mask<KK>(off, S, g0);
     __syncthreads();
 
@@ -742,7 +744,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
             octx[j] = k == BCLIP ? ix : ctx;
             // leaf: its clipped box; BEGIN_CLIP: likewise; END_CLIP: the
             // context inside its open.  Blend rows are filled in later.
-            res[j] = canon(isleaf || k == BCLIP ? ix : ctx);
+            res[j] = canon((isleaf && Pay<V>::kLeafOwn) || k == BCLIP ? ix : ctx);
         }
         const bool mism = (lclose && ((k == ECLIP) != (((clipm >> tps) & 1u) != 0))) ||
                           (rok && ((k == ECLIP) != (cur_kind == (int)BCLIP)));
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
         for (int j = 0; j < KK; ++j)
             if (((mkeep >> j) & 1u) && g0 + j < un) match[g0 + j] = mv[j];
     }
-    if (!BOXES) return;
+    if (!BOXES || !Pay<V>::kUnions) return;
 
     // ---- unions that cross threads or partitions.  Prefix and suffix
     // unions over threads come from wave scans plus the wave totals; only
@@ -1053,6 +1055,12 @@ struct SinkOut {
     __device__ __forceinline__ void emit(int64_t i, const Box &v) const { st_box(out, i, v); }
 };
 
+// Composition down the tree: each row's transform is written out.
+struct SinkAff {
+    void *out;
+    __device__ __forceinline__ void emit(int64_t i, const Aff &v) const { Pay<Aff>::st(out, i, v); }
+};
+
 // Backward: each coordinate of a non-EMPTY output row routes q(g) to its
 // attaining input element.  A row's own coordinates are flagged in a
 // per-row mask (no atomics); every other route is an exact 64-bit atomic add.
@@ -1221,8 +1229,10 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
         void *usuf = w + L.usuf;
         void *sp = w + L.sp;
         void *spb = w + L.spb;
-        k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp, spb);
-        k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
+        if (Pay<V>::kUnions) {
+            k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp, spb);
+            k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
+        }
         const int64_t gx = min((int64_t)(n + W - 1) / W, (int64_t)256 * 32);
         k_cross<V, SINK><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_cum, jv[cur], U_suf,
                                                       cr_slot, cr_c, cr_pre, upre, usuf, sp, spb, M,
@@ -1252,6 +1262,16 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
                                                 L, status, st);
     return run_pipeline<false, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w, L,
                                              status, st);
+}
+
+hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,
+                       uint32_t *status, hipStream_t st) {
+    const FwdLayout L = fwd_layout(n, 1, sizeof(Aff), false);
+    char *w = (char *)ws;
+    status = prep_status(w, L, nullptr, 1, n, status, st);
+    if (n == 0) return hipGetLastError();
+    return run_pipeline<true, Aff, SinkAff>(kind, (const float4 *)xf, n, nullptr, 1, nullptr, nullptr,
+                                            SinkAff{out}, w, L, status, st);
 }
 
 hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,

@@ -30,7 +30,7 @@ def lib():
 
 def test_header_declares_the_four_calls():
     fns = declared_functions()
-    for f in ("tb_match", "tb_bbox", "tb_bbox_backward", "tb_bbox_batched",
+    for f in ("tb_match", "tb_bbox", "tb_bbox_backward", "tb_bbox_batched", "tb_compose",
               "tb_workspace_bytes", "tb_status_str"):
         assert f in fns
 
@@ -44,7 +44,7 @@ def test_workspace_bytes(lib):
     f = lib.tb_workspace_bytes
     f.restype = ctypes.c_size_t
     f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
-    for op in (0, 1, 2, 3):
+    for op in (0, 1, 2, 3, 4):
         assert f(op, 0, 1) > 0
         a, b = f(op, 1000, 1), f(op, 1 << 20, 1)
         assert 0 < a < b
@@ -89,3 +89,17 @@ def test_argument_errors_return_before_device_work(lib):
     # workspace too small
     assert lib.tb_bbox(A, A, 10, A, A, A, 16, A, None) == TB_ERR_WORKSPACE
     assert lib.tb_bbox_backward(A, A, A, 10, A, A, 16, A, None) == TB_ERR_WORKSPACE
+
+
+def test_compose_argument_errors(lib):
+    P, I64, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.tb_compose.argtypes = [P, P, I64, P, P, SZ, P, P]
+    lib.tb_compose.restype = ctypes.c_int
+    A = 1 << 20
+    big = 1 << 40
+    assert lib.tb_compose(A, A, -1, A, A, big, A, None) == TB_ERR_SIZE
+    assert lib.tb_compose(A, None, 10, A, A, big, A, None) == TB_ERR_NULL
+    assert lib.tb_compose(A, A, 10, None, A, big, A, None) == TB_ERR_NULL
+    assert lib.tb_compose(A, A, 10, A, A, big, None, None) == TB_ERR_NULL
+    assert lib.tb_compose(A, A + 4, 10, A, A, big, A, None) == TB_ERR_ALIGN  # rows need 8 bytes
+    assert lib.tb_compose(A, A, 10, A, A, 16, A, None) == TB_ERR_WORKSPACE
