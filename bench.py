@@ -176,6 +176,30 @@ def match_section(steps, warmup, kind_np=None):
             "context": "the paper reports 13.5 Gelem/s for matching alone on a Radeon 5700 XT"}
 
 
+def compose_section(steps, warmup, kind_np=None):
+    """tb_compose (transforms composed down the tree) on the same scene:
+    kind 4 B + transform 24 B in, transform 24 B out per element."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    if kind_np is None:
+        kind_np = gen.config(2)["kind"]
+    n = len(kind_np)
+    kind = torch.from_numpy(kind_np.view(np.int32)).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(gen.SEED_BASE + 2)
+    xf = torch.randint(-(1 << 31), (1 << 31) - 1, (n, 6), dtype=torch.int32, device="cuda", generator=g)
+    out = torch.empty_like(xf)
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    ms = time_steps(lambda: tb.tb_compose(kind, xf, out=out, status=st), steps, warmup)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return {"workload": "scene-128M-chain32M", "elements": n, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(52 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +275,8 @@ def main():
         del kind, box, out, match
         torch.cuda.empty_cache()
         res["match_only"] = match_section(max(3, args.steps // 2), 2, host[0] if host else None)
+        torch.cuda.empty_cache()
+        res["compose"] = compose_section(max(3, args.steps // 2), 2, host[0] if host else None)
         torch.cuda.empty_cache()
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2)
         res["fwd_bwd"] = fwd_bwd_section(max(3, args.steps // 2), 2)
