@@ -43,6 +43,8 @@ def lib():
         L.tbg_batch.restype = I64
         L.tbg_normal.argtypes = [P, I64, U64]
         L.tbg_raw.argtypes = [P, I64, U64]
+        L.tbg_interleave.argtypes = [P, P, I64, I64, ctypes.c_uint32, U64, P, P]
+        L.tbg_interleave.restype = ctypes.c_int
         L.tbg_splitmix64.argtypes = [U64]
         L.tbg_splitmix64.restype = U64
         for f in (L.tbg_walk, L.tbg_walk_with_chains, L.tbg_chain_around_walk):
@@ -92,6 +94,24 @@ def batch(num_scenes, lg_lo, lg_hi, cap_lo, cap_hi, seed, box_mode=BOX_INDEP):
     return kind, box, offsets
 
 
+OTHER = 5  # tag of a stream element outside the tree
+
+
+def interleave(kind, box, n, seed, other=OTHER):
+    """Place the tree (kind, box) of m elements, in order, on a uniformly
+    random m-subset of n stream positions; the rest get tag `other` and a
+    random finite box.  Returns (tag, box, positions)."""
+    kind = np.ascontiguousarray(kind, dtype=np.uint32)
+    box = np.ascontiguousarray(box, dtype=np.float32).reshape(-1, 4)
+    m = kind.shape[0]
+    tag, sbox = _alloc(n)
+    rc = lib().tbg_interleave(kind.ctypes.data, box.ctypes.data, m, n, other, seed,
+                              tag.ctypes.data, sbox.ctypes.data)
+    assert rc == 0, rc
+    pos = np.flatnonzero(tag != other) if other > 4 else None
+    return tag, sbox, pos
+
+
 def normal(n, seed):
     out = np.zeros(n, dtype=np.float32)
     lib().tbg_normal(out.ctypes.data, n, seed)
@@ -137,3 +157,12 @@ def config(i, nested_boxes=False):
         g = normal(4 * n, splitmix64(seed)).reshape(n, 4)
         return dict(name="scene-16M-cap256-grad", kind=k, box=b, grad=g)
     raise ValueError(i)
+
+
+def stream_config(n=1 << 27, m=1 << 24, cap=64, seed=SEED_BASE + 16):
+    """Draw-object stream: a cap-`cap` random walk of m tree elements spread
+    over n stream positions (density m/n), every other position tagged OTHER."""
+    k, b = walk(m, cap, seed, BOX_INDEP)
+    tag, sbox, _ = interleave(k, b, n, splitmix64(seed))
+    return dict(name=f"stream-{n >> 20}M-tree{m >> 20}M" if m >= 1 << 20 else f"stream-{n}-tree{m}",
+                tag=tag, box=sbox, m=m)

@@ -343,3 +343,31 @@ void tbg_raw(uint64_t *out, int64_t n, uint64_t seed) {
     rng_seed(&r, seed);
     for (int64_t i = 0; i < n; ++i) out[i] = rng_next(&r);
 }
+
+/* A draw-object stream around a tree: the m tree elements (kind, box) keep
+ * their order and land on m of the n stream positions, each m-subset of
+ * positions equally likely (selection sampling, Knuth TAOCP vol. 2,
+ * Algorithm 3.4.2 S).  Every other position gets tag `other` and a box drawn
+ * uniformly in [-1000, 1000)^4 (finite, not ordered), which a consumer must
+ * ignore.  Returns 0, or -1 if m > n. */
+int tbg_interleave(const uint32_t *kind, const float *box, int64_t m, int64_t n, uint32_t other,
+                   uint64_t seed, uint32_t *tag_out, float *box_out) {
+    if (m < 0 || m > n) return -1;
+    rng_t r;
+    rng_seed(&r, seed);
+    int64_t need = m, j = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t left = n - i;
+        const int take = need > 0 && (double)left * rng_u01(&r) < (double)need;
+        if (take) {
+            tag_out[i] = kind[j];
+            memcpy(box_out + 4 * i, box + 4 * j, 4 * sizeof(float));
+            ++j;
+            --need;
+        } else {
+            tag_out[i] = other;
+            for (int c = 0; c < 4; ++c) box_out[4 * i + c] = (float)(2000.0 * rng_u01(&r) - 1000.0);
+        }
+    }
+    return 0;
+}

@@ -39,8 +39,9 @@ def lib():
         L.tbo_backward.argtypes = [P, P, P, I64, P]
         L.tbo_sources.argtypes = [P, P, I64, P]
         L.tbo_compose.argtypes = [P, P, I64, P]
+        L.tbo_bbox_stream.argtypes = [P, P, I64, P, P]
         for f in (L.tbo_bbox, L.tbo_match, L.tbo_bbox_f64, L.tbo_backward, L.tbo_sources,
-                  L.tbo_compose):
+                  L.tbo_compose, L.tbo_bbox_stream):
             f.restype = U32
         _lib = L
     return _lib
@@ -110,3 +111,18 @@ def compose(kind, xf):
     out = np.empty((n, 6), np.uint32)
     st = lib().tbo_compose(kind.ctypes.data, xf.ctypes.data, n, out.ctypes.data)
     return out, int(st)
+
+
+def bbox_stream(tag, box, match_init=None, out_init=None):
+    """Stream front end: extract the tree elements (tags 0..4), walk them,
+    put each result back at its stream position.  Positions tagged 5 keep
+    the values of match_init / out_init (default -7 and NaN, so an untouched
+    entry is recognisable).  Returns (match int32[n], out float32[n,4], status)."""
+    tag = _c(tag, np.uint32)
+    box = _c(box, np.float32).reshape(-1, 4)
+    n = tag.shape[0]
+    match = np.full(n, -7, np.int32) if match_init is None else np.array(match_init, np.int32)
+    out = np.full((n, 4), np.nan, np.float32) if out_init is None else np.array(out_init, np.float32)
+    st = lib().tbo_bbox_stream(tag.ctypes.data, box.ctypes.data, n, match.ctypes.data,
+                               out.ctypes.data)
+    return match, out, int(st)

@@ -382,3 +382,55 @@ uint32_t tbo_compose(const uint32_t *kind, const uint32_t *xf, int64_t n, uint32
     free(S);
     return status;
 }
+
+/*
+ * Draw-object stream front end (Introduction: the renderer first extracts
+ * just the clip and blend elements of its scene description by stream
+ * compaction, a prefix-sum application, and runs the bounding-box
+ * algorithm on the extracted sequence only).  Here the stream holds the
+ * tree's elements (tags 0..4: leaves take part in blend unions, so they are
+ * extracted too) among elements outside the tree (tag 5).
+ *   1. compaction: the tree elements, in stream order, with their positions;
+ *   2. the sequential walk (tbo_bbox) on the compacted sequence;
+ *   3. each result goes back to its element's stream position, and each
+ *      partner index is translated to a stream position.
+ * Rows and match entries at tag-5 positions are left as they were.  A tag
+ * above 5 raises BAD_KIND and is dropped like tag 5.
+ */
+enum { STREAM_OTHER = 5 };
+
+uint32_t tbo_bbox_stream(const uint32_t *tag, const float *box, int64_t n, int32_t *match,
+                         float *out) {
+    uint32_t status = 0;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (tag[i] <= END_BLEND) ++m;
+        else if (tag[i] != STREAM_OTHER) status |= ST_BAD_KIND;
+    }
+    const size_t mm = (size_t)(m > 0 ? m : 1);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * mm);
+    uint32_t *ck = (uint32_t *)malloc(sizeof(uint32_t) * mm);
+    float *cb = (float *)malloc(sizeof(float) * 4 * mm);
+    int32_t *cm = (int32_t *)malloc(sizeof(int32_t) * mm);
+    float *co = (float *)malloc(sizeof(float) * 4 * mm);
+    if (!pos || !ck || !cb || !cm || !co) {
+        free(pos), free(ck), free(cb), free(cm), free(co);
+        return 0x80000000u;
+    }
+    int64_t j = 0;
+    for (int64_t i = 0; i < n; ++i) { /* 1 */
+        if (tag[i] > END_BLEND) continue;
+        pos[j] = i;
+        ck[j] = tag[i];
+        memcpy(cb + 4 * j, box + 4 * i, 4 * sizeof(float));
+        ++j;
+    }
+    status |= tbo_bbox(ck, cb, m, cm, NULL, co); /* 2 */
+    for (j = 0; j < m; ++j) {                    /* 3 */
+        const int64_t i = pos[j];
+        if (match) match[i] = cm[j] >= 0 ? (int32_t)pos[cm[j]] : -1;
+        if (out) memcpy(out + 4 * i, co + 4 * j, 4 * sizeof(float));
+    }
+    free(pos), free(ck), free(cb), free(cm), free(co);
+    return status;
+}

@@ -85,3 +85,27 @@ def test_grid_boxes_exact():
     rows = np.isin(k, [0, 1])
     assert (np.floor(b[rows] * 256) == b[rows] * 256).all()
     assert (b[rows, 2] - b[rows, 0] >= 2.0 ** -8).all()
+
+
+def test_interleave_keeps_tree_order_and_is_seeded():
+    kind, box = gen.walk(500, 8, 31)
+    tag, sbox, pos = gen.interleave(kind, box, 2000, 32)
+    assert pos.shape == (500,) and np.all(np.diff(pos) > 0)
+    assert np.array_equal(tag[pos], kind) and np.array_equal(sbox[pos], box)
+    assert (np.delete(tag, pos) == gen.OTHER).all() and np.isfinite(sbox).all()
+    t2, b2, p2 = gen.interleave(kind, box, 2000, 32)
+    assert np.array_equal(t2, tag) and np.array_equal(b2, sbox)
+    t3, _, _ = gen.interleave(kind, box, 2000, 33)
+    assert not np.array_equal(t3, tag)
+    # each position is taken with probability m/n
+    hits = np.zeros(40)
+    k4 = np.zeros(10, np.uint32)
+    for s in range(2000):
+        t, _, _ = gen.interleave(k4, np.zeros((10, 4), np.float32), 40, 1000 + s)
+        hits += t != gen.OTHER
+    assert np.all(np.abs(hits / 2000 - 0.25) < 0.05)
+    # m == n and m == 0
+    t, _, p = gen.interleave(kind, box, 500, 34)
+    assert np.array_equal(t, kind)
+    t, _, p = gen.interleave(kind[:0], box[:0], 50, 35)
+    assert (t == gen.OTHER).all() and p.shape == (0,)
