@@ -200,6 +200,44 @@ def compose_section(steps, warmup, kind_np=None):
             "hbm_frac_alg": round(52 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def stream_section(steps, warmup):
+    """tb_bbox_stream on a draw-object stream of 2^27 elements holding a
+    cap-64 random-walk tree of 2^24 elements (density 1/8).  Algorithmic
+    bytes: every tag read once (4 B per stream element); per tree element its
+    box read, its row written (16 B each) and its partner written (4 B).  The
+    same tree already extracted, through tb_bbox, is timed beside it."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    w = gen.stream_config()
+    tag_np, box_np, m = w["tag"], w["box"], w["m"]
+    n = len(tag_np)
+    tag = torch.from_numpy(tag_np.view(np.int32)).cuda()
+    box = torch.from_numpy(box_np).cuda()
+    out = torch.empty_like(box)
+    match = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    ms = time_steps(lambda: tb.tb_bbox_stream(tag, box, match=match, out=out, status=st), steps,
+                    warmup)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    sel = tag_np <= 4
+    kind = torch.from_numpy(tag_np[sel].view(np.int32)).cuda()
+    cbox = torch.from_numpy(box_np[sel]).cuda()
+    del tag, box, out, match
+    cout = torch.empty_like(cbox)
+    cmatch = torch.empty(m, dtype=torch.int32, device="cuda")
+    ms_c = time_steps(lambda: tb.tb_bbox(kind, cbox, match=cmatch, out=cout, status=st), steps,
+                      warmup)
+    torch.cuda.synchronize()
+    alg = 4 * n + 36 * m
+    return {"workload": w["name"], "elements": n, "tree_elements": m,
+            "ms_per_step": round(ms, 4), "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "extracted_tree_alone_ms": round(ms_c, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,7 +248,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the path has no multi-GPU mode in this build", file=sys.stderr)
+              "the path has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -277,6 +315,7 @@ def main():
         res["match_only"] = match_section(max(3, args.steps // 2), 2, host[0] if host else None)
         torch.cuda.empty_cache()
         res["compose"] = compose_section(max(3, args.steps // 2), 2, host[0] if host else None)
+        res["stream"] = stream_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2)
         res["fwd_bwd"] = fwd_bwd_section(max(3, args.steps // 2), 2)

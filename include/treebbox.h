@@ -63,7 +63,8 @@ typedef enum {
     TB_BEGIN_CLIP = 1,
     TB_END_CLIP = 2,
     TB_BEGIN_BLEND = 3,
-    TB_END_BLEND = 4
+    TB_END_BLEND = 4,
+    TB_OTHER = 5 /* tb_bbox_stream only: a stream element outside the tree */
 } tb_kind;
 
 typedef struct {
@@ -98,6 +99,7 @@ typedef enum {
 #define TB_OP_BBOX_BACKWARD 2
 #define TB_OP_BBOX_BATCHED 3
 #define TB_OP_COMPOSE 4
+#define TB_OP_BBOX_STREAM 5
 
 /* Workspace bytes needed by `op` for n elements (num_scenes is used by
    TB_OP_BBOX_BATCHED only; pass 1 otherwise).  Returns 0 for invalid sizes. */
@@ -180,6 +182,29 @@ tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int6
  */
 tb_status tb_compose(const uint32_t *kind, const tb_affine *xf_in, int64_t n, tb_affine *xf_out,
                      void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
+ * Node boxes over a draw-object stream (Introduction: a renderer extracts
+ * just the tree's elements from its scene description by stream compaction,
+ * a prefix-sum application, and runs the algorithm on those only).  The
+ * stream holds the tree's elements (tags TB_LEAF .. TB_END_BLEND, leaves
+ * included since they enter blend unions) among elements outside the tree
+ * (TB_OTHER).  The result is tb_bbox on the tree elements in stream order,
+ * written back at their stream positions, with partners given as stream
+ * positions.  Rows and match entries at TB_OTHER positions are not written.
+ * A tag above TB_OTHER sets TB_DATA_BAD_KIND and is otherwise dropped like
+ * TB_OTHER.  The extraction happens on the device: no host synchronisation.
+ *   tag     [n]  uint32 tb_kind values, TB_OTHER allowed             (in)
+ *   box_in  [n]  tb_box; rows of LEAF and BEGIN_CLIP used            (in)
+ *   match   [n]  int32 partner stream position, -1 for LEAF         (out, nullable)
+ *   box_out [n]  tb_box node box per tree element                    (out)
+ *   dev_status [1] uint32                                            (out)
+ * Workspace: tb_workspace_bytes(TB_OP_BBOX_STREAM, n, 1) (sized for every
+ * element being a tree element).
+ */
+tb_status tb_bbox_stream(const uint32_t *tag, const tb_box *box_in, int64_t n, int32_t *match,
+                         tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
+                         void *stream);
 
 /*
  * Profiling hook: when both are non-NULL, later calls record `before` and

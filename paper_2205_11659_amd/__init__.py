@@ -19,9 +19,9 @@ import torch
 
 from ._build import LIB, build  # noqa: F401
 
-LEAF, BEGIN_CLIP, END_CLIP, BEGIN_BLEND, END_BLEND = range(5)
+LEAF, BEGIN_CLIP, END_CLIP, BEGIN_BLEND, END_BLEND, OTHER = range(6)
 DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS = 1, 2, 4, 8
-OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE = range(5)
+OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE, OP_BBOX_STREAM = range(6)
 
 _lib = None
 
@@ -45,7 +45,9 @@ def lib():
         L.tb_bbox_backward.argtypes = [P, P, P, I64, P, P, SZ, P, P]
         L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
         L.tb_compose.argtypes = [P, P, I64, P, P, SZ, P, P]
-        for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched, L.tb_compose):
+        L.tb_bbox_stream.argtypes = [P, P, I64, P, P, P, SZ, P, P]
+        for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched, L.tb_compose,
+                  L.tb_bbox_stream):
             f.restype = ctypes.c_int
         L.tb_status_str.argtypes = [ctypes.c_int]
         L.tb_status_str.restype = ctypes.c_char_p
@@ -187,6 +189,28 @@ def tb_compose(kind, xf, out=None, status=None):
     _check(lib().tb_compose(_ptr(kind), _ptr(xf), n, _ptr(out), ctypes.c_void_p(ws), wsb,
                             _ptr(status), _stream()))
     return out, status
+
+
+def tb_bbox_stream(tag, box, match=True, out=None, status=None):
+    """Node boxes over a draw-object stream: tags 0..4 are the tree's
+    elements, OTHER (5) marks elements outside the tree.  Returns (box_out
+    float32[n,4], match int32[n] or None, status int32[1]); rows and match
+    entries at OTHER positions are not written, so pass preallocated `out`
+    and `match` tensors to keep values there."""
+    tag = _as_kind(tag)
+    n = tag.numel()
+    box = _as_box(box, n)
+    dev = tag.device
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev) if out is None else out
+    if isinstance(match, torch.Tensor):
+        m = match
+    else:
+        m = torch.empty(n, dtype=torch.int32, device=dev) if match else None
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    ws, wsb = workspace(OP_BBOX_STREAM, n, 1, dev)
+    _check(lib().tb_bbox_stream(_ptr(tag), _ptr(box), n, _ptr(m), _ptr(out), ctypes.c_void_p(ws),
+                                wsb, _ptr(status), _stream()))
+    return out, m, status
 
 
 class TreeBBoxFn(torch.autograd.Function):

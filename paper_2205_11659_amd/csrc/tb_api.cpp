@@ -25,6 +25,8 @@ size_t ws_bytes_for(int op, int64_t n, int64_t S) {
         return tb::fwd_layout(n, 1, 32, true).total;
     case TB_OP_COMPOSE:
         return tb::fwd_layout(n, 1, 24, false).total;
+    case TB_OP_BBOX_STREAM:
+        return tb::stream_layout(n).total;
     default:
         return 0;
     }
@@ -86,6 +88,20 @@ tb_status tb_compose(const uint32_t *kind, const tb_affine *xf_in, int64_t n, tb
     tb_status c = check_common(kind, n, ws, ws_bytes, TB_OP_COMPOSE, 1);
     if (c != TB_OK) return c;
     return launched(tb::compose_run(kind, xf_in, n, xf_out, ws, dev_status, (hipStream_t)stream));
+}
+
+tb_status tb_bbox_stream(const uint32_t *tag, const tb_box *box_in, int64_t n, int32_t *match,
+                         tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
+                         void *stream) {
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!dev_status || (n > 0 && (!box_in || !box_out))) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (box_in && !aligned(box_in, 16)) ||
+        (box_out && !aligned(box_out, 16)) || (match && !aligned(match, 4)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(tag, n, ws, ws_bytes, TB_OP_BBOX_STREAM, 1);
+    if (c != TB_OK) return c;
+    return launched(tb::stream_run(tag, (const float4 *)box_in, n, match, (float4 *)box_out, ws,
+                                   dev_status, (hipStream_t)stream));
 }
 
 tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int64_t *offsets,

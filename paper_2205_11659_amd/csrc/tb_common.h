@@ -442,7 +442,8 @@ template <int KK>
 __device__ __forceinline__ void load_kinds(const uint32_t *kind, int64_t n, int64_t g0,
                                            uint32_t (&ks)[KK]) {
     static_assert(KK % 4 == 0, "kinds load in groups of four");
-    if (g0 + KK <= n) {
+    // 16-byte loads need a 16-byte aligned array (the caller's may be 4)
+    if (g0 + KK <= n && ((uintptr_t)kind & 15u) == 0) {
 #pragma unroll
         for (int q = 0; q < KK / 4; ++q) {
             const uint4 v = *reinterpret_cast<const uint4 *>(kind + g0 + 4 * q);

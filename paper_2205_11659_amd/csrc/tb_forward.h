@@ -27,11 +27,27 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
                    const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
                    void *ws, uint32_t *status, hipStream_t st);
 
-// Enqueue the gradient pass (recompute with attaining indices + exact sums).
 // Transform composition down the tree: xf and out hold 24-byte rows
 // [a b c d e f] (uint32, 8-byte aligned).
 hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,
                        uint32_t *status, hipStream_t st);
+
+// Draw-object stream front end: the forward pipeline's workspace for n
+// elements (the extracted count is at most n), then the extracted arrays.
+struct StreamLayout {
+    FwdLayout f;
+    int64_t nblk;
+    size_t ckind, cbox, cidx, cmatch, cnt, m;
+    size_t total;
+};
+StreamLayout stream_layout(int64_t n);
+
+// Extract the tree elements of a tag stream (tag 5: outside the tree), run
+// the forward pipeline on them, write rows and partners at stream positions.
+hipError_t stream_run(const uint32_t *tag, const float4 *box, int64_t n, int32_t *match,
+                      float4 *out, void *ws, uint32_t *status, hipStream_t st);
+
+// Enqueue the gradient pass (recompute with attaining indices + exact sums).
 hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,
                    float4 *grad_in, void *ws, uint32_t *status, hipStream_t st);
 

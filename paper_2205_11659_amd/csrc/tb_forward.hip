@@ -60,13 +60,21 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
                                               const float4 *__restrict__ box, int64_t n,
                                               const int64_t *__restrict__ off, int64_t S,
                                               int4 *__restrict__ pinfo,
-                                              int32_t *__restrict__ U_idx, void *__restrict__ U_cum) {
+                                              int32_t *__restrict__ U_idx, void *__restrict__ U_cum,
+                                              const int64_t *__restrict__ n_dyn) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
     __shared__ BicR sh_bic[NW];
     __shared__ V sh_b[NW];
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
     const int64_t P = blockIdx.x;
     const int64_t g0 = P * T + (int64_t)t * KK;
+    if (n_dyn) {  // element count known on the device only: later partitions are empty
+        n = *n_dyn;
+        if (P * T >= n) {
+            if (t == 0) pinfo[P] = make_int4(0, 0, 0, 0);
+            return;
+        }
+    }
 
     uint32_t ks[KK];
     load_kinds<KK>(kind, n, g0, ks);
@@ -450,7 +458,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     void *__restrict__ U_suf, const int *__restrict__ crbase, int32_t *__restrict__ cr_slot,
     int32_t *__restrict__ cr_c, void *__restrict__ cr_pre, void *__restrict__ ptot,
     int32_t *__restrict__ match, int32_t *__restrict__ pm, SINK sink,
-    uint32_t *__restrict__ status) {
+    uint32_t *__restrict__ status, const int64_t *__restrict__ n_dyn) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
     static_assert(!BOXES || KK == K, "the box path's unions are built for K elements per thread");
     __shared__ ResolveSmem<BOXES, V, KK> sm;
@@ -462,6 +470,13 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     const uint32_t M = gridDim.x;
     const uint32_t p0 = P * T;
     const uint32_t g0 = p0 + (uint32_t)t * KK;
+    if (n_dyn) {  // element count known on the device only
+        n = *n_dyn;
+        if ((int64_t)p0 >= n) {  // an empty partition: its leaf union is EMPTY
+            if (BOXES && Pay<V>::kUnions && t == 0) Pay<V>::st(ptot, P, Pay<V>::empty());
+            return;
+        }
+    }
     const uint32_t un = (uint32_t)n;
     const int4 myp = part[P];
     const int dP = myp.x;
@@ -1055,6 +1070,19 @@ struct SinkOut {
     __device__ __forceinline__ void emit(int64_t i, const Box &v) const { st_box(out, i, v); }
 };
 
+// Stream front end: rows of the extracted sequence go to their elements'
+// stream positions (idx[i] < ns; any other value is dropped, which only
+// stale workspace entries of malformed input can hold).
+struct SinkScatter {
+    float4 *out;
+    const int32_t *idx;
+    uint32_t ns;
+    __device__ __forceinline__ void emit(int64_t i, const Box &v) const {
+        const uint32_t j = (uint32_t)idx[i];
+        if (j < ns) st_box(out, j, v);
+    }
+};
+
 // Composition down the tree: each row's transform is written out.
 struct SinkAff {
     void *out;
@@ -1112,6 +1140,142 @@ __global__ void k_grad_final(const float4 *__restrict__ g, const unsigned long l
 __global__ void k_zero_u64(unsigned long long *p, int64_t cnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) p[i] = 0ull;
+}
+
+// ------------------------------------------------- draw-object stream front end
+// The tree's elements (tags 0..4) are extracted from a stream that also
+// holds elements outside the tree (tag 5) by stream compaction, a prefix-sum
+// application (Introduction); the pipeline then runs on the extracted
+// sequence only.  Blocks of CT stream elements: count, an exclusive scan of
+// the block counts, scatter.  Inside a block, element order is round q
+// (1024 elements each), then thread, then the thread's 4 consecutive
+// elements, so each round is one 16-byte load per thread.
+constexpr int CW = 256;          // threads per compaction block
+constexpr int CR = 4;            // rounds of 4 elements per thread
+constexpr int CT = CW * 4 * CR;  // stream elements per block
+constexpr uint32_t TAG_OTHER = 5;
+
+// Tags of round q for this thread; past the end reads as TAG_OTHER.
+__device__ __forceinline__ void load_tags4(const uint32_t *tag, int64_t n, int64_t e0,
+                                           uint32_t (&v)[4]) {
+    if (e0 + 4 <= n && ((uintptr_t)tag & 15u) == 0) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(tag + e0);
+        v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = e0 + c < n ? tag[e0 + c] : TAG_OTHER;
+    }
+}
+
+__global__ __launch_bounds__(CW) void k_cmp_count(const uint32_t *__restrict__ tag, int64_t n,
+                                                  int *__restrict__ cnt,
+                                                  uint32_t *__restrict__ status) {
+    __shared__ int sh[CW / WAVE];
+    const int t = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * CT;
+    int c = 0;
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < CR; ++q) {
+        uint32_t v[4];
+        load_tags4(tag, n, b0 + q * (CW * 4) + 4 * t, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c += v[j] <= 4u ? 1 : 0;
+            bad |= v[j] > TAG_OTHER;
+        }
+    }
+    if (bad) flag(status, nullptr, 1, 0, ST_BAD_KIND);
+    int tot;
+    block_excl_scan<CW / WAVE>(c, AddOp{}, 0, sh, &tot);
+    if (t == 0) cnt[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of the nblk block counts in place, in
+// chunks of 1024 threads x 8 counts; the total goes to *m.
+__global__ __launch_bounds__(1024) void k_cmp_scan(int *__restrict__ cnt, int64_t nblk,
+                                                   int64_t *__restrict__ m) {
+    __shared__ int sh[1024 / WAVE];
+    const int t = threadIdx.x;
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblk; c0 += 1024 * 8) {
+        int v[8], s = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t i = c0 + (int64_t)t * 8 + j;
+            v[j] = i < nblk ? cnt[i] : 0;
+            s += v[j];
+        }
+        int tot;
+        const int ex = block_excl_scan<1024 / WAVE>(s, AddOp{}, 0, sh, &tot);
+        int64_t run = carry + ex;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t i = c0 + (int64_t)t * 8 + j;
+            if (i < nblk) cnt[i] = (int)run;
+            run += v[j];
+        }
+        carry += tot;
+    }
+    if (t == 0) *m = carry;
+}
+
+// Scatter the tree elements of each block to their extracted positions:
+// kind, stream index, and the box of leaves and clip opens (the only rows
+// the pipeline reads).
+__global__ __launch_bounds__(CW) void k_cmp_scatter(const uint32_t *__restrict__ tag,
+                                                    const float4 *__restrict__ box, int64_t n,
+                                                    const int *__restrict__ boff,
+                                                    uint32_t *__restrict__ ckind,
+                                                    float4 *__restrict__ cbox,
+                                                    int32_t *__restrict__ cidx) {
+    __shared__ int grp[CR * (CW / WAVE)];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * CT;
+    uint32_t v[CR][4];
+    int lex[CR];  // tree elements of earlier lanes of this wave, per round
+#pragma unroll
+    for (int q = 0; q < CR; ++q) {
+        load_tags4(tag, n, b0 + q * (CW * 4) + 4 * t, v[q]);
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c += v[q][j] <= 4u ? 1 : 0;
+        int wt;
+        lex[q] = wave_excl_scan(c, AddOp{}, 0, &wt);
+        if (lane == 0) grp[q * (CW / WAVE) + wid] = wt;
+    }
+    __syncthreads();
+    const int64_t base = boff[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < CR; ++q) {
+        int o = 0;  // groups (round, wave) before this one, in element order
+#pragma unroll
+        for (int g = 0; g < CR * (CW / WAVE); ++g)
+            if (g < q * (CW / WAVE) + wid) o += grp[g];
+        int64_t d = base + o + lex[q];
+        const int64_t e0 = b0 + q * (CW * 4) + 4 * t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t k = v[q][j];
+            if (k > 4u) continue;
+            ckind[d] = k;
+            cidx[d] = (int32_t)(e0 + j);
+            if (k == LEAF || k == BCLIP) cbox[d] = box[e0 + j];
+            ++d;
+        }
+    }
+}
+
+// Partners of the extracted sequence, translated to stream positions.
+__global__ void k_stream_match(const int32_t *__restrict__ cmatch,
+                               const int32_t *__restrict__ cidx, const int64_t *__restrict__ m,
+                               int32_t *__restrict__ match) {
+    const int64_t mm = *m;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < mm;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = cmatch[c];
+        match[cidx[c]] = (p >= 0 && p < mm) ? cidx[p] : -1;
+    }
 }
 
 // ----------------------------------------------------------------- driver
@@ -1173,7 +1337,7 @@ template <bool BOXES, class V, class SINK>
 static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t n,
                                const int64_t *off, int64_t S, int32_t *match, int32_t *pm,
                                SINK sink, char *w, const FwdLayout &L, uint32_t *status,
-                               hipStream_t st) {
+                               hipStream_t st, const int64_t *n_dyn = nullptr) {
     const int64_t M = L.M;
     int4 *pinfo = (int4 *)(w + L.pinfo);
     int4 *part = (int4 *)(w + L.part);
@@ -1183,7 +1347,8 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     int32_t *U_idx = (int32_t *)(w + L.U_idx);
     void *U_cum = w + L.U_cum;
     constexpr int KD = BOXES ? K : 8;  // elements per thread of the reduce
-    k_reduce<BOXES, V, KD><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum);
+    k_reduce<BOXES, V, KD><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum,
+                                                              n_dyn);
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
@@ -1222,7 +1387,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     k_resolve<BOXES, V, SINK, KR><<<(unsigned)M, T / KR, 0, st>>>(kind, box, n, off, S, pinfo, part, runs,
                                                          rhead, jv[cur], U_idx, U_cum, U_suf,
                                                          crbase, cr_slot, cr_c, cr_pre, ptot, match,
-                                                         pm, sink, status);
+                                                         pm, sink, status, n_dyn);
     if (prof) (void)hipEventRecord(g_prof_after, st);
     if (BOXES) {
         void *upre = w + L.upre;
@@ -1272,6 +1437,53 @@ hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *ou
     if (n == 0) return hipGetLastError();
     return run_pipeline<true, Aff, SinkAff>(kind, (const float4 *)xf, n, nullptr, 1, nullptr, nullptr,
                                             SinkAff{out}, w, L, status, st);
+}
+
+StreamLayout stream_layout(int64_t n) {
+    StreamLayout S{};
+    S.f = fwd_layout(n, 1, sizeof(Box), false);
+    const int64_t nn = n > 0 ? n : 1;
+    S.nblk = (nn + CT - 1) / CT;
+    size_t o = S.f.total;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += al(bytes);
+        return r;
+    };
+    S.ckind = take(sizeof(uint32_t) * nn);
+    S.cbox = take(sizeof(float4) * nn);
+    S.cidx = take(sizeof(int32_t) * nn);
+    S.cmatch = take(sizeof(int32_t) * nn);
+    S.cnt = take(sizeof(int) * S.nblk);
+    S.m = take(sizeof(int64_t));
+    S.total = o;
+    return S;
+}
+
+hipError_t stream_run(const uint32_t *tag, const float4 *box, int64_t n, int32_t *match,
+                      float4 *out, void *ws, uint32_t *status, hipStream_t st) {
+    const StreamLayout S = stream_layout(n);
+    char *w = (char *)ws;
+    status = prep_status(w, S.f, nullptr, 1, n, status, st);
+    if (n == 0) return hipGetLastError();
+    uint32_t *ckind = (uint32_t *)(w + S.ckind);
+    float4 *cbox = (float4 *)(w + S.cbox);
+    int32_t *cidx = (int32_t *)(w + S.cidx);
+    int32_t *cmatch = (int32_t *)(w + S.cmatch);
+    int *cnt = (int *)(w + S.cnt);
+    int64_t *m = (int64_t *)(w + S.m);
+    k_cmp_count<<<(unsigned)S.nblk, CW, 0, st>>>(tag, n, cnt, status);
+    k_cmp_scan<<<1, 1024, 0, st>>>(cnt, S.nblk, m);
+    k_cmp_scatter<<<(unsigned)S.nblk, CW, 0, st>>>(tag, box, n, cnt, ckind, cbox, cidx);
+    // the pipeline is launched for n elements; partitions past the extracted
+    // count m (read on the device) exit at once
+    hipError_t e = run_pipeline<true, Box, SinkScatter>(
+        ckind, cbox, n, nullptr, 1, match ? cmatch : nullptr, nullptr,
+        SinkScatter{out, cidx, (uint32_t)n}, w, S.f, status, st, m);
+    if (e != hipSuccess || !match) return e;
+    const unsigned g = (unsigned)min((n + 255) / 256, (int64_t)256 * 16);
+    k_stream_match<<<g, 256, 0, st>>>(cmatch, cidx, m, match);
+    return hipGetLastError();
 }
 
 hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,

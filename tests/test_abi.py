@@ -31,6 +31,7 @@ def lib():
 def test_header_declares_the_four_calls():
     fns = declared_functions()
     for f in ("tb_match", "tb_bbox", "tb_bbox_backward", "tb_bbox_batched", "tb_compose",
+              "tb_bbox_stream",
               "tb_workspace_bytes", "tb_status_str"):
         assert f in fns
 
@@ -44,11 +45,12 @@ def test_workspace_bytes(lib):
     f = lib.tb_workspace_bytes
     f.restype = ctypes.c_size_t
     f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
-    for op in (0, 1, 2, 3, 4):
+    for op in (0, 1, 2, 3, 4, 5):
         assert f(op, 0, 1) > 0
         a, b = f(op, 1000, 1), f(op, 1 << 20, 1)
         assert 0 < a < b
     assert f(2, 1 << 20, 1) > f(1, 1 << 20, 1)  # gradient payload is larger
+    assert f(5, 1 << 20, 1) > f(1, 1 << 20, 1)  # the stream adds its extracted arrays
     assert f(1, -1, 1) == 0 and f(1, 1 << 31, 1) == 0
     assert f(3, 100, 0) == 0 and f(9, 100, 1) == 0
 
@@ -103,3 +105,26 @@ def test_compose_argument_errors(lib):
     assert lib.tb_compose(A, A, 10, A, A, big, None, None) == TB_ERR_NULL
     assert lib.tb_compose(A, A + 4, 10, A, A, big, A, None) == TB_ERR_ALIGN  # rows need 8 bytes
     assert lib.tb_compose(A, A, 10, A, A, 16, A, None) == TB_ERR_WORKSPACE
+
+
+def test_stream_argument_errors(lib):
+    P, I64, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.tb_bbox_stream.argtypes = [P, P, I64, P, P, P, SZ, P, P]
+    lib.tb_bbox_stream.restype = ctypes.c_int
+    A = 1 << 20
+    big = 1 << 40
+    f = lib.tb_bbox_stream
+    assert f(A, A, -1, A, A, A, big, A, None) == TB_ERR_SIZE
+    assert f(A, A, 1 << 31, A, A, A, big, A, None) == TB_ERR_SIZE
+    assert f(None, A, 10, A, A, A, big, A, None) == TB_ERR_NULL
+    assert f(A, None, 10, A, A, A, big, A, None) == TB_ERR_NULL
+    assert f(A, A, 10, A, None, A, big, A, None) == TB_ERR_NULL
+    assert f(A, A, 10, A, A, A, big, None, None) == TB_ERR_NULL
+    assert f(A + 2, A, 10, A, A, A, big, A, None) == TB_ERR_ALIGN
+    assert f(A, A + 4, 10, A, A, A, big, A, None) == TB_ERR_ALIGN
+    assert f(A, A, 10, A + 2, A, A, big, A, None) == TB_ERR_ALIGN
+    assert f(A, A, 10, A, A, A, 16, A, None) == TB_ERR_WORKSPACE
+    lib.tb_workspace_bytes.restype = SZ
+    lib.tb_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
+    need = lib.tb_workspace_bytes(5, 10, 1)
+    assert f(A, A, 10, A, A, A, need - 1, A, None) == TB_ERR_WORKSPACE
