@@ -245,11 +245,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
+    ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd"],
+                    help="run one secondary section alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the path has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        fn = {"stream": stream_section, "match": match_section, "compose": compose_section,
+              "batched": batched_section, "fwd_bwd": fwd_bwd_section}[args.only]
+        print(json.dumps({args.only: fn(args.steps, args.warmup)}), flush=True)
+        return
 
     import torch
 

@@ -1149,11 +1149,15 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t cnt) {
 // sequence only.  Blocks of CT stream elements: count, an exclusive scan of
 // the block counts, scatter.  Inside a block, element order is round q
 // (1024 elements each), then thread, then the thread's 4 consecutive
-// elements, so each round is one 16-byte load per thread.
+// elements, so each round is one 16-byte load per thread.  The pipeline
+// writes rows straight to stream positions; partners are translated after.
 constexpr int CW = 256;          // threads per compaction block
-constexpr int CR = 4;            // rounds of 4 elements per thread
+constexpr int CR = 8;            // rounds of 4 elements per thread
 constexpr int CT = CW * 4 * CR;  // stream elements per block
 constexpr uint32_t TAG_OTHER = 5;
+// Word 3 of a raw (stride 0) buffer resource on gfx9-family chips: 32-bit
+// data format, no swizzle; out-of-range offsets read as zero.
+constexpr int BUF_DWORD3 = 0x00020000;
 
 // Tags of round q for this thread; past the end reads as TAG_OTHER.
 __device__ __forceinline__ void load_tags4(const uint32_t *tag, int64_t n, int64_t e0,
@@ -1171,24 +1175,32 @@ __global__ __launch_bounds__(CW) void k_cmp_count(const uint32_t *__restrict__ t
                                                   int *__restrict__ cnt,
                                                   uint32_t *__restrict__ status) {
     __shared__ int sh[CW / WAVE];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
     const int64_t b0 = (int64_t)blockIdx.x * CT;
+    uint32_t v[CR][4];
+#pragma unroll
+    for (int q = 0; q < CR; ++q) load_tags4(tag, n, b0 + q * (CW * 4) + 4 * t, v[q]);
     int c = 0;
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < CR; ++q) {
-        uint32_t v[4];
-        load_tags4(tag, n, b0 + q * (CW * 4) + 4 * t, v);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            c += v[j] <= 4u ? 1 : 0;
-            bad |= v[j] > TAG_OTHER;
+            c += v[q][j] <= 4u ? 1 : 0;
+            bad |= v[q][j] > TAG_OTHER;
         }
     }
     if (bad) flag(status, nullptr, 1, 0, ST_BAD_KIND);
-    int tot;
-    block_excl_scan<CW / WAVE>(c, AddOp{}, 0, sh, &tot);
-    if (t == 0) cnt[blockIdx.x] = tot;
+    int wt;
+    wave_excl_scan(c, AddOp{}, 0, &wt);
+    if (lane == 0) sh[wid] = wt;
+    __syncthreads();
+    if (t == 0) {
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < CW / WAVE; ++w) tot += sh[w];
+        cnt[blockIdx.x] = tot;
+    }
 }
 
 // One workgroup: exclusive scan of the nblk block counts in place, in
@@ -1233,10 +1245,11 @@ __global__ __launch_bounds__(CW) void k_cmp_scatter(const uint32_t *__restrict__
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
     const int64_t b0 = (int64_t)blockIdx.x * CT;
     uint32_t v[CR][4];
+#pragma unroll
+    for (int q = 0; q < CR; ++q) load_tags4(tag, n, b0 + q * (CW * 4) + 4 * t, v[q]);
     int lex[CR];  // tree elements of earlier lanes of this wave, per round
 #pragma unroll
     for (int q = 0; q < CR; ++q) {
-        load_tags4(tag, n, b0 + q * (CW * 4) + 4 * t, v[q]);
         int c = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) c += v[q][j] <= 4u ? 1 : 0;
@@ -1245,13 +1258,34 @@ __global__ __launch_bounds__(CW) void k_cmp_scatter(const uint32_t *__restrict__
         if (lane == 0) grp[q * (CW / WAVE) + wid] = wt;
     }
     __syncthreads();
-    const int64_t base = boff[blockIdx.x];
+    // boxes through a buffer resource over this block's rows: a lane that
+    // needs no box passes an out-of-range offset, which reads zero without a
+    // memory access, so the gathers need no branches (and no waits between)
+    const int64_t rem = n - b0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(box + b0), (short)0, (int)((rem < CT ? rem : CT) * (int64_t)sizeof(float4)),
+        BUF_DWORD3);
+    float4 bq[CR][4];  // every gather is issued before the first store
 #pragma unroll
     for (int q = 0; q < CR; ++q) {
-        int o = 0;  // groups (round, wave) before this one, in element order
 #pragma unroll
-        for (int g = 0; g < CR * (CW / WAVE); ++g)
-            if (g < q * (CW / WAVE) + wid) o += grp[g];
+        for (int j = 0; j < 4; ++j) {
+            const bool need = v[q][j] == LEAF || v[q][j] == BCLIP;
+            const int off = need ? (q * (CW * 4) + 4 * t + j) * (int)sizeof(float4) : -1;
+            bq[q][j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        }
+    }
+    const int64_t base = boff[blockIdx.x];
+    int rb = 0;  // tree elements in the rounds before this one
+#pragma unroll
+    for (int q = 0; q < CR; ++q) {
+        int o = rb;  // ... plus those of this round's earlier waves
+#pragma unroll
+        for (int w = 0; w < CW / WAVE; ++w) {
+            const int gw = grp[q * (CW / WAVE) + w];
+            if (w < wid) o += gw;
+            rb += gw;
+        }
         int64_t d = base + o + lex[q];
         const int64_t e0 = b0 + q * (CW * 4) + 4 * t;
 #pragma unroll
@@ -1260,21 +1294,32 @@ __global__ __launch_bounds__(CW) void k_cmp_scatter(const uint32_t *__restrict__
             if (k > 4u) continue;
             ckind[d] = k;
             cidx[d] = (int32_t)(e0 + j);
-            if (k == LEAF || k == BCLIP) cbox[d] = box[e0 + j];
+            if (k == LEAF || k == BCLIP) cbox[d] = bq[q][j];
             ++d;
         }
     }
 }
 
-// Partners of the extracted sequence, translated to stream positions.
+// Partners of the extracted sequence, translated to stream positions; four
+// per thread and round so that the dependent gathers overlap.
 __global__ void k_stream_match(const int32_t *__restrict__ cmatch,
                                const int32_t *__restrict__ cidx, const int64_t *__restrict__ m,
                                int32_t *__restrict__ match) {
     const int64_t mm = *m;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < mm;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p = cmatch[c];
-        match[cidx[c]] = (p >= 0 && p < mm) ? cidx[p] : -1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c0 < mm; c0 += 4 * stride) {
+        int32_t p[4], i[4], q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + u * stride;
+            p[u] = c < mm ? cmatch[c] : -1;
+            i[u] = c < mm ? cidx[c] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = (p[u] >= 0 && p[u] < mm) ? cidx[p[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + u * stride < mm) match[i[u]] = q[u];
     }
 }
 
