@@ -65,6 +65,8 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
     __shared__ BicR sh_bic[NW];
     __shared__ V sh_b[NW];
+    __shared__ int32_t sh_ui[T];
+    __shared__ V sh_uc[BOXES ? T : 1];
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
     const int64_t P = blockIdx.x;
     const int64_t g0 = P * T + (int64_t)t * KK;
@@ -148,6 +150,8 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
             if (w < wid) cum = isect(sh_b[w], cum);
     }
 
+    // surviving opens fill slots [0, tot.b): staged in LDS, then written
+    // with consecutive lanes on consecutive slots
     const int64_t slot0 = (int64_t)base - baseP;  // first surviving open's slot
     int jj = 0;
 #pragma unroll
@@ -156,11 +160,17 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
         const int64_t slot = slot0 + jj;
         ++jj;
         if (slot < 0 || slot >= T) continue;
-        U_idx[P * T + slot] = (int32_t)((uint32_t)(g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
+        sh_ui[slot] = (int32_t)((uint32_t)(g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
         if (BOXES) {
             cum = isect(cum, bxs[p]);  // the identity unless a clip
-            Pay<V>::st(U_cum, P * T + slot, cum);
+            sh_uc[slot] = cum;
         }
+    }
+    __syncthreads();
+    const int nsv = tot.b < T ? tot.b : T;
+    for (int sl = t; sl < nsv; sl += WW) {
+        U_idx[P * T + sl] = sh_ui[sl];
+        if (BOXES) Pay<V>::st(U_cum, P * T + sl, sh_uc[sl]);
     }
     if (t == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
 }
