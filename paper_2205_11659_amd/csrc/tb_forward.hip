@@ -86,15 +86,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     const uint32_t rm = reset_mask<KK>(off, S, g0);
     const Walk wk = walk_kinds<KK>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
-    // boxes of this thread's unmatched clip opens, issued before the scans
-    // (those that do not survive the partition are read and dropped)
     V bxs[KK];
-    if (BOXES) {
-#pragma unroll
-        for (int p = 0; p < KK; ++p)
-            bxs[p] = (((wk.umask >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::in(box, g0 + p)
-                                                                 : Pay<V>::inf();
-    }
 
     // prefix (earlier threads) and suffix (later threads) products
     BicR wtot, wtot2;
@@ -135,6 +127,10 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     }
     V cum = Pay<V>::inf();
     if (BOXES) {
+        // boxes of the clip opens that survive the partition
+#pragma unroll
+        for (int p = 0; p < KK; ++p)
+            bxs[p] = (((surv >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::in(box, g0 + p) : Pay<V>::inf();
         V agg = Pay<V>::inf();
 #pragma unroll
         for (int p = 0; p < KK; ++p)
