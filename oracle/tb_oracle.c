@@ -23,7 +23,7 @@
  *  - The union is stored at the close and copied to the open (section "GPU
  *    implementation of clipping and blending", last paragraph).
  *
- * Readings where the paper is silent (each also listed in the design doc):
+ * Readings where the paper is silent:
  *  - EMPTY = (+inf,+inf,-inf,-inf); a box is kept only if x0<x1 && y0<y1,
  *    otherwise it becomes EMPTY ("canon").  The whole-plane root clip context
  *    is INF = (-inf,-inf,+inf,+inf).
