@@ -99,7 +99,58 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def batched_section(steps, warmup):
+def oracle_scenes_threads(kind_np, box_np, offsets, reps=3):
+    """The oracle over the scenes of a batch on a thread pool (ctypes releases
+    the GIL during each call), one scene per task; median of `reps` passes."""
+    import concurrent.futures
+
+    import oracle
+    try:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    S = len(offsets) - 1
+
+    def one(sc):
+        a, b = int(offsets[sc]), int(offsets[sc + 1])
+        oracle.bbox(kind_np[a:b], box_np[a:b])
+
+    order = np.argsort(-np.diff(np.asarray(offsets)), kind="stable")  # largest scenes first
+    times = []
+    with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(one, order.tolist()))
+            times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    n = int(offsets[-1])
+    return {"value": round(n / med / 1e9, 4), "unit": "Gelem/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {S} scenes ({n} elements), one scene per task, largest first, "
+                      f"median of {reps} passes"}
+
+
+def copy_ceiling():
+    """A plain device copy of 1 GiB (read + write) timed with HIP events: the
+    practical bandwidth ceiling beside the 8 TB/s peak."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 10
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    return {"gbs": round(nbytes / (ms / 1e3) / 1e9, 1), "bytes_moved": nbytes,
+            "frac_of_peak": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def batched_section(steps, warmup, cpu=False):
     """2048 ragged scenes: one tb_bbox_batched launch vs one graph-captured
     tb_bbox call per scene (same rows, byte-compared)."""
     import torch
@@ -123,6 +174,8 @@ def batched_section(steps, warmup):
                 "batched_ms": round(ms_b, 4), "batched_gelem_s": round(n / ms_b / 1e6, 3),
                 "per_scene_graph_ms": round(ms_g, 4), "per_scene_graph_gelem_s": round(n / ms_g / 1e6, 3),
                 "speedup": round(ms_g / ms_b, 3), "byte_identical": same})
+    if cpu:
+        out["cpu_baseline_threads"] = oracle_scenes_threads(c["kind"], c["box"], c["offsets"])
     return out
 
 
@@ -324,8 +377,10 @@ def main():
         res["compose"] = compose_section(max(3, args.steps // 2), 2, host[0] if host else None)
         res["stream"] = stream_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
-        res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2)
+        res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2, cpu=not args.no_cpu)
         res["fwd_bwd"] = fwd_bwd_section(max(3, args.steps // 2), 2)
+        torch.cuda.empty_cache()
+        res["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(*host)
     print(json.dumps(res), flush=True)
