@@ -129,6 +129,42 @@ def oracle_scenes_threads(kind_np, box_np, offsets, reps=3):
                       f"median of {reps} passes"}
 
 
+def small_section(reps=100):
+    """The 65,536-element scene (cap 64): launch-latency bound, so one tb_bbox
+    call is captured in a HIP graph and replayed `reps` times."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    c = gen.config(0)
+    n = len(c["kind"])
+    kind, box = torch.from_numpy(c["kind"].view(np.int32)).cuda(), torch.from_numpy(c["box"]).cuda()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    match = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    tb.tb_bbox(kind, box, match=match, out=out, status=st)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            tb.tb_bbox(kind, box, match=match, out=out, status=st)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(5):
+        graph.replay()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    us = a.elapsed_time(b) * 1e3 / reps
+    return {"workload": c["name"], "elements": n, "us_per_call": round(us, 2),
+            "gelem_s": round(n / us / 1e3, 3), "timing": f"HIP graph of one call, {reps} replays"}
+
+
 def copy_ceiling():
     """A plain device copy of 1 GiB (read + write) timed with HIP events: the
     practical bandwidth ceiling beside the 8 TB/s peak."""
@@ -298,7 +334,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
-    ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd"],
+    ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small"],
                     help="run one secondary section alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -307,7 +343,8 @@ def main():
         sys.exit(2)
     if args.only:
         fn = {"stream": stream_section, "match": match_section, "compose": compose_section,
-              "batched": batched_section, "fwd_bwd": fwd_bwd_section}[args.only]
+              "batched": batched_section, "fwd_bwd": fwd_bwd_section,
+              "small": lambda st, w: small_section()}[args.only]
         print(json.dumps({args.only: fn(args.steps, args.warmup)}), flush=True)
         return
 
@@ -380,6 +417,7 @@ def main():
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2, cpu=not args.no_cpu)
         res["fwd_bwd"] = fwd_bwd_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
+        res["small_scene"] = small_section()
         res["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(*host)
