@@ -342,6 +342,38 @@ __global__ void k_jump(const int32_t *__restrict__ ptr_in, const void *__restric
     Pay<V>::st(val_out, P, v);
 }
 
+// All rounds at once when the partitions fit one workgroup (M <= JS): the
+// links and values live in LDS between rounds, so a small scene pays one
+// launch instead of one per round.  Writes the result back in place.
+constexpr int JS = 1024;
+template <class V>
+__global__ __launch_bounds__(JS) void k_jump_small(int32_t *__restrict__ ptr, void *__restrict__ val,
+                                                   int64_t M, int rounds) {
+    __shared__ int32_t sp[JS];
+    __shared__ V sv[JS];
+    const int P = threadIdx.x;
+    int32_t p = -1;
+    V v = Pay<V>::inf();
+    if (P < M) {
+        p = ptr[P];
+        v = Pay<V>::ld(val, P);
+    }
+    for (int r = 0; r < rounds; ++r) {
+        sp[P] = p;
+        sv[P] = v;
+        __syncthreads();
+        if (p >= 0) {
+            v = isect(sv[p], v);  // ancestor first
+            p = sp[p];
+        }
+        __syncthreads();
+    }
+    if (P < M) {
+        ptr[P] = p;
+        Pay<V>::st(val, P, v);
+    }
+}
+
 // ---------------------------------------------------------------- k_runs
 // Owner runs of each partition's incoming levels [max(preM,1), dP]: walking
 // the owner links from P-1, each owner R holds a contiguous range of levels
@@ -1417,9 +1449,13 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     if (BOXES) {
         int rounds = 0;
         while (((int64_t)1 << rounds) < M) ++rounds;
-        for (int r = 0; r < rounds; ++r) {
-            k_jump<V><<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
-            cur ^= 1;
+        if (M <= JS) {
+            if (rounds > 0) k_jump_small<V><<<1, JS, 0, st>>>(jp[0], jv[0], M, rounds);
+        } else {
+            for (int r = 0; r < rounds; ++r) {
+                k_jump<V><<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
+                cur ^= 1;
+            }
         }
     }
     int4 *runs = (int4 *)(w + L.runs);
@@ -1447,7 +1483,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
         void *spb = w + L.spb;
         if (Pay<V>::kUnions) {
             k_ublocks<V><<<(unsigned)L.nb, UB, 0, st>>>(ptot, M, upre, usuf, sp, spb);
-            k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
+            if (L.levels > 1) k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
         }
         const int64_t gx = min((int64_t)(n + W - 1) / W, (int64_t)256 * 32);
         k_cross<V, SINK><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_cum, jv[cur], U_suf,
