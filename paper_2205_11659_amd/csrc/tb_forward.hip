@@ -233,11 +233,16 @@ __global__ __launch_bounds__(SB) void k_spine_top(int4 *__restrict__ bagg, int64
 }
 
 // blocks cover [0, Mp): partition records, min-tree leaves and the block's
-// subtree (padding leaves hold INT32_MAX)
+// subtree (padding leaves hold INT32_MAX).  With `single` (all partitions in
+// one block) the block offsets are zero and this kernel also does the top
+// kernel's work, so a small scene skips two launches.
 __global__ __launch_bounds__(SB) void k_spine_apply(const int4 *__restrict__ pinfo, int64_t M,
                                                     const int4 *__restrict__ bex,
                                                     int4 *__restrict__ part, int *__restrict__ mtree,
-                                                    int64_t Mp, int *__restrict__ crbase) {
+                                                    int64_t Mp, int *__restrict__ crbase, bool single,
+                                                    const int64_t *__restrict__ off, int64_t S,
+                                                    int64_t n, uint32_t *__restrict__ status,
+                                                    int *__restrict__ crtot) {
     __shared__ Seg sh[SB / WAVE];
     __shared__ int shi[SB / WAVE];
     __shared__ int lt[SB];
@@ -250,9 +255,13 @@ __global__ __launch_bounds__(SB) void k_spine_apply(const int4 *__restrict__ pin
     const Seg loc = block_excl_scan<SB / WAVE>(v, SegOp{}, Seg{0, 0}, sh, &tot);
     int atot;
     const int aloc = block_excl_scan<SB / WAVE>(P < M ? pv.x : 0, AddOp{}, 0, shi, &atot);
+    if (single && t == 0) {
+        *crtot = atot;
+        if (tot.v != 0 && n > 0) flag(status, off, S, n - 1, ST_UNBAL);
+    }
     int cm = INT32_MAX;
     if (P < M) {
-        const int4 bx = bex[B];
+        const int4 bx = single ? make_int4(0, 0, 0, 0) : bex[B];
         crbase[P] = bx.z + aloc;
         const Seg ex = SegOp{}(Seg{bx.x, bx.y}, loc);
         const int d = ex.v;
@@ -1435,10 +1444,14 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
-        k_spine_blocks<<<(unsigned)nbk, SB, 0, st>>>(pinfo, M, bagg);
-        k_spine_top<<<1, SB, 0, st>>>(bagg, nbk, off, S, n, status, crtot);
         const int64_t nbt = (L.Mp + SB - 1) / SB;
-        k_spine_apply<<<(unsigned)nbt, SB, 0, st>>>(pinfo, M, bagg, part, mtree, L.Mp, crbase);
+        const bool single = nbt == 1;  // all partitions (and tree leaves) in one block
+        if (!single) {
+            k_spine_blocks<<<(unsigned)nbk, SB, 0, st>>>(pinfo, M, bagg);
+            k_spine_top<<<1, SB, 0, st>>>(bagg, nbk, off, S, n, status, crtot);
+        }
+        k_spine_apply<<<(unsigned)nbt, SB, 0, st>>>(pinfo, M, bagg, part, mtree, L.Mp, crbase, single,
+                                                    off, S, n, status, crtot);
         if (L.Mp > SB) k_spine_treetop<<<1, SB, 0, st>>>(mtree, L.Mp);
     }
     int32_t *jp[2] = {(int32_t *)(w + L.jptr0), (int32_t *)(w + L.jptr1)};
