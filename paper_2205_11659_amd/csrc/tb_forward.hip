@@ -10,15 +10,19 @@
 //                 slice" (section "Simple GPU parentheses matching
 //                 algorithm", Stack slices; boxes per section "GPU
 //                 implementation of clipping and blending").
-//   k_spine_scan  segmented depth scan over partitions; min tree of the
-//                 partitions' lowest levels.
+//   k_spine_blocks / k_spine_top / k_spine_apply (/ k_spine_treetop)
+//                 segmented depth scan over partitions; min tree of the
+//                 partitions' lowest levels.  One launch of k_spine_apply
+//                 when all partitions fit one block.
 //   k_spine_link  owner link of each partition: the nearest earlier
 //                 partition whose lowest level is smaller (it holds the
 //                 stack entry just below); seeds pointer jumping.
 //   k_jump        pointer jumping along owner links: the clip context at
 //                 each partition's base level (the paper's pointer jumping,
 //                 section "Parallel bounding boxes", Clips, applied to
-//                 partitions instead of elements).
+//                 partitions instead of elements).  k_jump_small does all
+//                 rounds in one launch when the partitions fit one block.
+//   k_runs        the owner runs of each partition's incoming levels.
 //   k_resolve     per partition: reads kinds and boxes once, rebuilds the
 //                 incoming stack levels it pops (suffix relation, section
 //                 "The stack monoid"), resolves matches, clips and blend
@@ -30,6 +34,12 @@
 //                 close's prefix, written at both rows (the union stored at
 //                 the open as well as the close, last paragraph of "GPU
 //                 implementation of clipping and blending").
+//
+// The same kernels serve the gradient pass (a (value, index) payload), the
+// transform composition (an affine payload) and batched scenes (resets at
+// scene starts).  The draw-object stream front end (k_cmp_count,
+// k_cmp_scan, k_cmp_scatter, k_stream_match) extracts the tree's elements
+// before the pipeline and translates the partners after it.
 #include "tb_common.h"
 #include "tb_forward.h"
 
