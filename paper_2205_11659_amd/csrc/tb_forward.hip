@@ -20,9 +20,10 @@
 //   k_jump        pointer jumping along owner links: the clip context at
 //                 each partition's base level (the paper's pointer jumping,
 //                 section "Parallel bounding boxes", Clips, applied to
-//                 partitions instead of elements).  k_jump_small does all
-//                 rounds in one launch when the partitions fit one block.
+//                 partitions instead of elements).
 //   k_runs        the owner runs of each partition's incoming levels.
+//                 k_link_small does the links, the jumping and the runs in
+//                 one launch when the partitions fit one block.
 //   k_resolve     per partition: reads kinds and boxes once, rebuilds the
 //                 incoming stack levels it pops (suffix relation, section
 //                 "The stack monoid"), resolves matches, clips and blend
@@ -320,6 +321,31 @@ __device__ __forceinline__ int64_t gtree_prev_less(const int *mt, int64_t Mp, in
     return -1;
 }
 
+// One partition's owner link (written to part[P].w) and, for payloads, the
+// seed of pointer jumping: the context entry just below its base level.
+template <bool BOXES, class V>
+__device__ __forceinline__ void spine_link_one(int64_t P, const int4 *__restrict__ pinfo,
+                                               int4 *__restrict__ part, const int *__restrict__ mtree,
+                                               int64_t Mp, const void *__restrict__ U_cum,
+                                               int32_t &ptr_out, V &val_out) {
+    const int4 pr = part[P];
+    const int64_t cm = pr.y;
+    int64_t link = -1;
+    if (cm != SENT) link = gtree_prev_less(mtree, Mp, P, cm);
+    part[P].w = (int)link;
+    V val = Pay<V>::inf();
+    int64_t ptr = -1;
+    if (BOXES && cm != SENT && cm > 0 && link >= 0) {
+        const int64_t slot = cm - (int64_t)part[link].z - 1;
+        if (slot >= 0 && slot < pinfo[link].y) {
+            val = Pay<V>::ld(U_cum, link * T + slot);
+            ptr = link;
+        }
+    }
+    ptr_out = (int32_t)ptr;
+    val_out = val;
+}
+
 template <bool BOXES, class V>
 __global__ void k_spine_link(const int4 *__restrict__ pinfo, int4 *__restrict__ part, int64_t M,
                              const int *__restrict__ mtree, int64_t Mp,
@@ -327,22 +353,11 @@ __global__ void k_spine_link(const int4 *__restrict__ pinfo, int4 *__restrict__ 
                              void *__restrict__ jval) {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= M) return;
-    int4 pr = part[P];
-    const int64_t cm = pr.y;
-    int64_t link = -1;
-    if (cm != SENT) link = gtree_prev_less(mtree, Mp, P, cm);
-    part[P].w = (int)link;
+    int32_t ptr;
+    V val;
+    spine_link_one<BOXES, V>(P, pinfo, part, mtree, Mp, U_cum, ptr, val);
     if (!BOXES) return;
-    V val = Pay<V>::inf();
-    int64_t ptr = -1;
-    if (cm != SENT && cm > 0 && link >= 0) {
-        const int64_t slot = cm - (int64_t)part[link].z - 1;
-        if (slot >= 0 && slot < pinfo[link].y) {
-            val = Pay<V>::ld(U_cum, link * T + slot);
-            ptr = link;
-        }
-    }
-    jptr[P] = (int32_t)ptr;
+    jptr[P] = ptr;
     Pay<V>::st(jval, P, val);
 }
 
@@ -361,37 +376,7 @@ __global__ void k_jump(const int32_t *__restrict__ ptr_in, const void *__restric
     Pay<V>::st(val_out, P, v);
 }
 
-// All rounds at once when the partitions fit one workgroup (M <= JS): the
-// links and values live in LDS between rounds, so a small scene pays one
-// launch instead of one per round.  Writes the result back in place.
-constexpr int JS = 1024;
-template <class V>
-__global__ __launch_bounds__(JS) void k_jump_small(int32_t *__restrict__ ptr, void *__restrict__ val,
-                                                   int64_t M, int rounds) {
-    __shared__ int32_t sp[JS];
-    __shared__ V sv[JS];
-    const int P = threadIdx.x;
-    int32_t p = -1;
-    V v = Pay<V>::inf();
-    if (P < M) {
-        p = ptr[P];
-        v = Pay<V>::ld(val, P);
-    }
-    for (int r = 0; r < rounds; ++r) {
-        sp[P] = p;
-        sv[P] = v;
-        __syncthreads();
-        if (p >= 0) {
-            v = isect(sv[p], v);  // ancestor first
-            p = sp[p];
-        }
-        __syncthreads();
-    }
-    if (P < M) {
-        ptr[P] = p;
-        Pay<V>::st(val, P, v);
-    }
-}
+constexpr int JS = 1024;  // partitions handled by one workgroup in k_link_small
 
 // ---------------------------------------------------------------- k_runs
 // Owner runs of each partition's incoming levels [max(preM,1), dP]: walking
@@ -399,10 +384,9 @@ __global__ __launch_bounds__(JS) void k_jump_small(int32_t *__restrict__ ptr, vo
 // (its surviving opens).  One thread per partition; many chains are walked
 // at once, which hides the dependent loads.  Up to RMAX runs are stored;
 // head = {count, next owner, next top level, complete}.
-__global__ void k_runs(const int4 *__restrict__ pinfo, const int4 *__restrict__ part, int64_t M,
-                       int4 *__restrict__ runs, int4 *__restrict__ rhead) {
-    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (P >= M) return;
+__device__ __forceinline__ void runs_one(int64_t P, const int4 *__restrict__ pinfo,
+                                         const int4 *__restrict__ part, int4 *__restrict__ runs,
+                                         int4 *__restrict__ rhead) {
     const int64_t dP = part[P].x;
     const int64_t preM = dP - pinfo[P].x;
     const int64_t need_lo = preM > 1 ? preM : 1;
@@ -421,6 +405,49 @@ __global__ void k_runs(const int4 *__restrict__ pinfo, const int4 *__restrict__ 
     }
     const bool complete = !(R >= 0 && hi >= need_lo);
     rhead[P] = make_int4(nr, (int)R, (int)hi, complete ? 1 : 0);
+}
+
+__global__ void k_runs(const int4 *__restrict__ pinfo, const int4 *__restrict__ part, int64_t M,
+                       int4 *__restrict__ runs, int4 *__restrict__ rhead) {
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P < M) runs_one(P, pinfo, part, runs, rhead);
+}
+
+// Links, pointer jumping and owner runs in one launch when the partitions
+// fit one block (M <= JS): the links are published to the block by a
+// barrier, and the jumping rounds run in LDS.
+template <bool BOXES, class V>
+__global__ __launch_bounds__(JS) void k_link_small(const int4 *__restrict__ pinfo,
+                                                   int4 *__restrict__ part, int64_t M,
+                                                   const int *__restrict__ mtree, int64_t Mp,
+                                                   const void *__restrict__ U_cum,
+                                                   int32_t *__restrict__ jptr, void *__restrict__ jval,
+                                                   int rounds, int4 *__restrict__ runs,
+                                                   int4 *__restrict__ rhead) {
+    __shared__ int32_t sp[JS];
+    __shared__ V sv[BOXES ? JS : 1];
+    const int P = threadIdx.x;
+    int32_t p = -1;
+    V v = Pay<V>::inf();
+    if (P < M) spine_link_one<BOXES, V>(P, pinfo, part, mtree, Mp, U_cum, p, v);
+    __syncthreads();  // every link is in part[].w
+    if (BOXES) {
+        for (int r = 0; r < rounds; ++r) {
+            sp[P] = p;
+            sv[P] = v;
+            __syncthreads();
+            if (p >= 0) {
+                v = isect(sv[p], v);  // ancestor first
+                p = sp[p];
+            }
+            __syncthreads();
+        }
+        if (P < M) {
+            jptr[P] = p;
+            Pay<V>::st(jval, P, v);
+        }
+    }
+    if (P < M) runs_one(P, pinfo, part, runs, rhead);
 }
 
 // ------------------------------------------------------------- k_resolve
@@ -1467,23 +1494,24 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     int32_t *jp[2] = {(int32_t *)(w + L.jptr0), (int32_t *)(w + L.jptr1)};
     void *jv[2] = {w + L.jval0, w + L.jval1};
     const unsigned gM = (unsigned)((M + 255) / 256);
-    k_spine_link<BOXES, V><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
+    int4 *runs = (int4 *)(w + L.runs);
+    int4 *rhead = (int4 *)(w + L.rhead);
+    int rounds = 0;
+    while (((int64_t)1 << rounds) < M) ++rounds;
     int cur = 0;
-    if (BOXES) {
-        int rounds = 0;
-        while (((int64_t)1 << rounds) < M) ++rounds;
-        if (M <= JS) {
-            if (rounds > 0) k_jump_small<V><<<1, JS, 0, st>>>(jp[0], jv[0], M, rounds);
-        } else {
+    if (M <= JS) {  // links, jumping and runs in one launch
+        k_link_small<BOXES, V><<<1, JS, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0],
+                                                 rounds, runs, rhead);
+    } else {
+        k_spine_link<BOXES, V><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
+        if (BOXES) {
             for (int r = 0; r < rounds; ++r) {
                 k_jump<V><<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
                 cur ^= 1;
             }
         }
+        k_runs<<<gM, 256, 0, st>>>(pinfo, part, M, runs, rhead);
     }
-    int4 *runs = (int4 *)(w + L.runs);
-    int4 *rhead = (int4 *)(w + L.rhead);
-    k_runs<<<gM, 256, 0, st>>>(pinfo, part, M, runs, rhead);
     void *U_suf = w + L.U_suf;
     int32_t *cr_slot = (int32_t *)(w + L.cr_slot);
     int32_t *cr_c = (int32_t *)(w + L.cr_c);
