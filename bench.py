@@ -165,9 +165,11 @@ def small_section(reps=100):
             "gelem_s": round(n / us / 1e3, 3), "timing": f"HIP graph of one call, {reps} replays"}
 
 
-def copy_ceiling():
+def copy_ceiling(reps=10):
     """A plain device copy of 1 GiB (read + write) timed with HIP events: the
-    practical bandwidth ceiling beside the 8 TB/s peak."""
+    practical bandwidth ceiling beside the 8 TB/s peak.  The same copy,
+    profiled with the FETCH_SIZE and WRITE_SIZE counters (`--only copy`),
+    calibrates those counters: true bytes / counted bytes per dispatch."""
     import torch
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -175,15 +177,50 @@ def copy_ceiling():
         dst.copy_(src)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    for _ in range(10):
+    for _ in range(reps):
         dst.copy_(src)
     b.record()
     torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / 10
+    ms = a.elapsed_time(b) / reps
     nbytes = 2 * src.numel() * 4
     del src, dst
     return {"gbs": round(nbytes / (ms / 1e3) / 1e9, 1), "bytes_moved": nbytes,
-            "frac_of_peak": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "bytes_read_per_copy": nbytes // 2, "frac_of_peak": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def gpu_clocks():
+    """Current GPU clocks as rocm-smi reports them (recorded with the run)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=30)
+        d = json.loads(r.stdout)
+        card = d.get("card0") or next(iter(d.values()))
+        return {k: v for k, v in card.items() if "clock" in k.lower() or "sclk" in k.lower()
+                or "mclk" in k.lower() or "fclk" in k.lower()}
+    except Exception as e:  # a missing tool or unexpected output is reported, not fatal
+        return {"error": str(e)[:200]}
+
+
+def c1_section(steps, warmup):
+    """The 2^24-element scene with 16 chains of depth 100,000 in a cap-16
+    walk: forward throughput (reported, not graded)."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    c = gen.config(1)
+    n = len(c["kind"])
+    kind, box = torch.from_numpy(c["kind"].view(np.int32)).cuda(), torch.from_numpy(c["box"]).cuda()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    m = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    ms = time_steps(lambda: tb.tb_bbox(kind, box, match=m, out=out, status=st), steps, warmup)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return {"workload": c["name"], "elements": n, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(ALG_BYTES_FWD * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def batched_section(steps, warmup, cpu=False):
@@ -216,7 +253,10 @@ def batched_section(steps, warmup, cpu=False):
 
 
 def fwd_bwd_section(steps, warmup):
-    """Forward + backward on the 2^24-element gradient workload."""
+    """Forward + backward on the 2^24-element gradient workload, through the
+    autograd.Function (TreeBBoxFn): out = bbox(kind, box); out.backward(g).
+    Status checks are off inside the timed loop (each would synchronise);
+    the status words are checked once after it."""
     import torch
 
     import gen
@@ -224,20 +264,24 @@ def fwd_bwd_section(steps, warmup):
     c = gen.config(4)
     n = len(c["kind"])
     kind = torch.from_numpy(c["kind"].view(np.int32)).cuda()
-    box = torch.from_numpy(c["box"]).cuda()
+    box = torch.from_numpy(c["box"]).cuda().requires_grad_(True)
     g = torch.from_numpy(c["grad"]).cuda()
-    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
-    m = torch.empty(n, dtype=torch.int32, device="cuda")
-    st = torch.empty(1, dtype=torch.int32, device="cuda")
 
     def step():
-        tb.tb_bbox(kind, box, match=m, out=out, status=st)
-        tb.tb_bbox_backward(kind, box, g)
+        box.grad = None
+        out, _, st = tb.TreeBBoxFn.apply(kind, box, False)
+        out.backward(g)
+        return st
 
     ms = time_steps(step, steps, warmup)
+    st = step()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    ms_f = time_steps(lambda: tb.TreeBBoxFn.apply(kind, box.detach(), False), steps, warmup)
     return {"workload": "scene-16M-cap256-grad", "elements": n, "ms_per_step": round(ms, 4),
             "gelem_s": round(n / ms / 1e6, 3),
-            "hbm_frac_alg": round(92 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "hbm_frac_alg": round(92 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "forward_only_ms": round(ms_f, 4), "via": "TreeBBoxFn (autograd)"}
 
 
 def match_section(steps, warmup, kind_np=None):
@@ -334,7 +378,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
-    ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small"],
+    ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small",
+                                       "c1", "copy"],
                     help="run one secondary section alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -343,8 +388,9 @@ def main():
         sys.exit(2)
     if args.only:
         fn = {"stream": stream_section, "match": match_section, "compose": compose_section,
-              "batched": batched_section, "fwd_bwd": fwd_bwd_section,
-              "small": lambda st, w: small_section()}[args.only]
+              "batched": batched_section, "fwd_bwd": fwd_bwd_section, "c1": c1_section,
+              "small": lambda st, w: small_section(),
+              "copy": lambda st, w: copy_ceiling(max(st, 1))}[args.only]
         print(json.dumps({args.only: fn(args.steps, args.warmup)}), flush=True)
         return
 
@@ -369,20 +415,30 @@ def main():
     torch.cuda.synchronize()
     assert int(status.item()) == 0, f"status {int(status.item())}"
 
+    clocks_before = gpu_clocks()
     ev = HipEvents()
     pairs = [(ev.create(), ev.create()) for _ in range(args.steps)]
+    # whole-step events on the stream the calls run on (torch's current one)
+    steps_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         tb.lib().tb_profile_events(pairs[k][0], pairs[k][1])
+        steps_ev[k][0].record()
         tb.tb_bbox(kind, box, match=match, out=out, status=status)
+        steps_ev[k][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tb.lib().tb_profile_events(None, None)
     assert int(status.item()) == 0
     k_ms = float(np.mean([ev.elapsed_ms(a, b) for a, b in pairs]))
+    ev_ms = np.array([a.elapsed_time(b) for a, b in steps_ev])
+    clocks_after = gpu_clocks()
 
     ms_step = wall * 1e3 / args.steps
-    value = n / (ms_step / 1e3) / 1e9
+    med_ms = float(np.median(ev_ms))
+    value = n / (med_ms / 1e3) / 1e9
     achieved = ALG_BYTES_FWD * n / (k_ms / 1e3) / 1e9
     res = {
         "metric": "Gelem/s + % HBM peak, match+bbox fwd(+bwd); batched vs per-scene launches",
@@ -400,7 +456,11 @@ def main():
         "config": {"workload": "scene-128M-chain32M", "elements": n,
                    "structure": "chain of 2^25 alternating clip/blend opens around a cap-64 "
                                 "random walk of 2^26 elements", "op": "tb_bbox forward"},
-        "path_hbm_frac": round(ALG_BYTES_FWD * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_ms": {"median": round(med_ms, 4), "min": round(float(ev_ms.min()), 4),
+                    "wall_mean": round(ms_step, 4),
+                    "timing": "value from the median of per-step HIP events on the call's stream"},
+        "path_hbm_frac": round(ALG_BYTES_FWD * n / (med_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "gpu_clocks": {"before": clocks_before, "after": clocks_after},
         "roofline": {"bound": "hbm", "kernel": "k_resolve", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "kernel_ms": round(k_ms, 4), "traffic": measured_traffic(),
@@ -416,6 +476,8 @@ def main():
         torch.cuda.empty_cache()
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2, cpu=not args.no_cpu)
         res["fwd_bwd"] = fwd_bwd_section(max(3, args.steps // 2), 2)
+        torch.cuda.empty_cache()
+        res["c1"] = c1_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
         res["small_scene"] = small_section()
         res["copy_ceiling"] = copy_ceiling()

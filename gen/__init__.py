@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "treegen.c")
 LIB_PATH = os.path.join(_HERE, "libtreegen.so")
 
-BOX_INDEP, BOX_NESTED, BOX_GRID, BOX_NESTED_ALL = 0, 1, 2, 3
+BOX_INDEP, BOX_NESTED, BOX_GRID, BOX_NESTED_ALL, BOX_INSET, BOX_INSET_ND = 0, 1, 2, 3, 4, 5
 SEED_BASE = 0x7B0B0000
 
 _lib = None
@@ -134,22 +134,25 @@ C1_CHAINS, C1_DEPTH, C1_LEAVES = 16, 100_000, 8
 
 
 def config(i, nested_boxes=False):
+    """Workload i.  nested_boxes=True swaps the independent boxes of the
+    walks for BOX_INSET boxes (non-empty clip contexts, 5% of walk clips
+    disjoint from their parent); the 2^27 chain scene always uses them."""
     seed = SEED_BASE + i
     if i == 0:  # 65,536 elements, depth cap 64
-        k, b = walk(65536, 64, seed, BOX_NESTED_ALL if nested_boxes else BOX_INDEP)
+        k, b = walk(65536, 64, seed, BOX_INSET if nested_boxes else BOX_INDEP)
         return dict(name="scene-64K-cap64", kind=k, box=b)
     if i == 1:  # 2^24: depth<=16 walk with 16 embedded chains of depth 100,000
         n = 1 << 24
         n_walk = n - C1_CHAINS * (2 * C1_DEPTH + C1_LEAVES)
         k, b = walk_with_chains(n_walk, 16, C1_CHAINS, C1_DEPTH, C1_LEAVES, seed,
-                                BOX_NESTED_ALL if nested_boxes else BOX_INDEP)
+                                BOX_INSET if nested_boxes else BOX_INDEP)
         return dict(name="scene-16M-chains100K", kind=k, box=b)
     if i == 2:  # 2^27: chain of depth 2^25 around a 2^26 cap-64 walk
-        k, b = chain_around_walk(1 << 25, 1 << 26, 64, seed, BOX_NESTED)
+        k, b = chain_around_walk(1 << 25, 1 << 26, 64, seed, BOX_INSET)
         return dict(name="scene-128M-chain32M", kind=k, box=b)
     if i == 3:  # 2048 ragged scenes, sizes 2^U[6,18], caps U{4..4096}
         k, b, off = batch(2048, 6.0, 18.0, 4, 4096, seed,
-                          BOX_NESTED_ALL if nested_boxes else BOX_INDEP)
+                          BOX_INSET if nested_boxes else BOX_INDEP)
         return dict(name="batch-2048-ragged", kind=k, box=b, offsets=off)
     if i == 4:  # 2^24, cap 256, grid coordinates, N(0,1) upstream gradient
         n = 1 << 24

@@ -72,7 +72,8 @@ static inline int64_t rng_int(rng_t *r, int64_t lo, int64_t hi) {
 }
 
 /* ------------------------------------------------------------ builder */
-enum { BOX_INDEP = 0, BOX_NESTED = 1, BOX_GRID = 2, BOX_NESTED_ALL = 3 };
+enum { BOX_INDEP = 0, BOX_NESTED = 1, BOX_GRID = 2, BOX_NESTED_ALL = 3, BOX_INSET = 4,
+       BOX_INSET_ND = 5 };
 
 typedef struct {
     uint32_t *kind;
@@ -80,9 +81,13 @@ typedef struct {
     int64_t n, pos;
     int64_t *stk;      /* positions of currently open elements */
     int64_t *clipanc;  /* per stack level: position of nearest clip at or below it, or -1 */
+    int64_t *reg;      /* BOX_INSET*: per stack level, 4 grid coordinates of the region
+                          its children are drawn in */
     int64_t sp, cap_stk;
     int box_mode;
-    double p_disjoint; /* BOX_NESTED: probability that a box misses its clip ancestor */
+    double p_disjoint; /* BOX_NESTED, BOX_INSET: probability that a clip misses its parent */
+    int in_chain;      /* BOX_INSET*: the opens being emitted form a nested chain */
+    int chain_first;   /* ... and the chain's first clip is still to come */
     rng_t r;
 } builder;
 
@@ -95,10 +100,13 @@ static int b_init(builder *b, uint32_t *kind, float *box, int64_t n, int64_t max
     b->cap_stk = max_depth + 2;
     b->stk = (int64_t *)malloc(sizeof(int64_t) * (size_t)b->cap_stk);
     b->clipanc = (int64_t *)malloc(sizeof(int64_t) * (size_t)b->cap_stk);
-    if (!b->stk || !b->clipanc) return -1;
+    b->reg = (int64_t *)malloc(sizeof(int64_t) * 4 * (size_t)b->cap_stk);
+    if (!b->stk || !b->clipanc || !b->reg) return -1;
     b->sp = 0;
     b->box_mode = box_mode;
-    b->p_disjoint = 0.05;
+    b->p_disjoint = box_mode == BOX_INSET_ND ? 0.0 : 0.05;
+    b->in_chain = 0;
+    b->chain_first = 0;
     rng_seed(&b->r, seed);
     return 0;
 }
@@ -106,6 +114,126 @@ static int b_init(builder *b, uint32_t *kind, float *box, int64_t n, int64_t max
 static void b_free(builder *b) {
     free(b->stk);
     free(b->clipanc);
+    free(b->reg);
+}
+
+/*
+ * BOX_INSET / BOX_INSET_ND: value-rich nested boxes on a 2^-8 grid (all
+ * coordinates are integers times 2^-8 below 2^13 in magnitude, so exact in
+ * fp32).  Every node's box is drawn around an inner box that lies inside
+ * the region of its nearest clip ancestor; a clip's inner box is the region
+ * of its own subtree.  Regions therefore nest, so every clip context and
+ * every leaf stays non-empty, while each drawn box sticks out of the region
+ * on some sides and is cut there by some ancestor clip.  The generator only
+ * draws sub-intervals of intervals; it forms no intersection or union.
+ *  - Root region: [256, 3840]^2.
+ *  - Leaf: inner box of size Exp(64) (at least one grid step, at most the
+ *    region) at a uniform position in the region; it sticks out on x0 with
+ *    probability 1/8, on x1 and y1 with probability 1/2 (by 1 + Exp(16)
+ *    capped at 255 units), never on y0.
+ *  - Clip in a walk: inner box of U[1/2, 1) times the region's size at a
+ *    uniform position; sticks out on each side with probability 1/2.  With
+ *    probability p_disjoint (BOX_INSET: 0.05, BOX_INSET_ND: 0) the clip is
+ *    moved 8192 units left, away from every other box, so its subtree is
+ *    empty.
+ *  - Clip in a nested chain: the inner box is the region with side c moved
+ *    in by one grid step with probability 1/256, 1/4096, 1/65536, 0 for
+ *    x0, y0, x1, y1 (a side moved in is "tight": the clip does not stick out
+ *    there); the chain's first clip is tight on all sides; other sides stick
+ *    out by 1 + Exp(4) units.  So the running clip context along a chain is
+ *    set by the latest tight clip on each side, which on y1 is the chain's
+ *    first clip, however deep the chain.
+ */
+#define INSET_G 256.0 /* grid steps per unit */
+
+static int64_t g_ext(rng_t *r, double mean_units) {
+    double e = floor(rng_exp(r, mean_units) * INSET_G);
+    if (e > 254.0 * INSET_G) e = 254.0 * INSET_G;
+    return (int64_t)INSET_G + (int64_t)e;
+}
+
+/* the region children of the current top are drawn in (a blend level holds
+   its parent's region) */
+static void inset_region(builder *b, int64_t rg[4]) {
+    if (b->sp > 0) {
+        memcpy(rg, b->reg + 4 * (b->sp - 1), 4 * sizeof(int64_t));
+    } else {
+        rg[0] = rg[1] = (int64_t)(256 * INSET_G);
+        rg[2] = rg[3] = (int64_t)(3840 * INSET_G);
+    }
+}
+
+/* a sub-interval of [lo, hi] of length len (1 <= len <= hi - lo), uniform */
+static int64_t g_place(rng_t *r, int64_t lo, int64_t hi, int64_t len) {
+    return lo + (int64_t)floor(rng_u01(r) * (double)(hi - lo - len + 1));
+}
+
+static void inset_store(float *dst, const int64_t c[4]) {
+    for (int q = 0; q < 4; ++q) dst[q] = (float)((double)c[q] / INSET_G);
+}
+
+/* draws element i (a leaf or a clip open); a clip's inner box goes to inner */
+static void draw_inset(builder *b, uint32_t k, float *dst, int64_t inner[4]) {
+    rng_t *r = &b->r;
+    int64_t rg[4], in[4], c[4];
+    inset_region(b, rg);
+    const int64_t rw = rg[2] - rg[0], rh = rg[3] - rg[1];
+    if (k == K_LEAF) {
+        int64_t w = (int64_t)ceil(rng_exp(r, 64.0) * INSET_G), h = (int64_t)ceil(rng_exp(r, 64.0) * INSET_G);
+        if (w < 1) w = 1;
+        if (h < 1) h = 1;
+        if (w > rw) w = rw;
+        if (h > rh) h = rh;
+        in[0] = g_place(r, rg[0], rg[2], w);
+        in[1] = g_place(r, rg[1], rg[3], h);
+        in[2] = in[0] + w;
+        in[3] = in[1] + h;
+        c[0] = in[0] - (rng_u01(r) < 0.125 ? g_ext(r, 16.0) : 0);
+        c[1] = in[1];
+        c[2] = in[2] + (rng_u01(r) < 0.5 ? g_ext(r, 16.0) : 0);
+        c[3] = in[3] + (rng_u01(r) < 0.5 ? g_ext(r, 16.0) : 0);
+        inset_store(dst, c);
+        return;
+    }
+    if (b->in_chain) {
+        static const double p_tight[4] = {1.0 / 256, 1.0 / 4096, 1.0 / 65536, 0.0};
+        const int first = b->chain_first;
+        b->chain_first = 0;
+        for (int q = 0; q < 4; ++q) {
+            const int lowside = q < 2;
+            const int64_t span = rg[q < 2 ? q + 2 : q] - rg[q < 2 ? q : q - 2];
+            int tight = first;
+            in[q] = rg[q];
+            if (rng_u01(r) < p_tight[q] && span > 4) {
+                in[q] += lowside ? 1 : -1;
+                tight = 1;
+            }
+            const int64_t e = tight ? 0 : g_ext(r, 4.0);
+            c[q] = lowside ? in[q] - e : in[q] + e;
+        }
+        /* a side moves in only while the region spans more than 4 steps, so
+           the inner box keeps at least 3 steps per axis */
+    } else {
+        int64_t w = (int64_t)floor((double)rw * (0.5 + 0.5 * rng_u01(r)));
+        int64_t h = (int64_t)floor((double)rh * (0.5 + 0.5 * rng_u01(r)));
+        if (w < 1) w = 1;
+        if (h < 1) h = 1;
+        in[0] = g_place(r, rg[0], rg[2], w);
+        in[1] = g_place(r, rg[1], rg[3], h);
+        in[2] = in[0] + w;
+        in[3] = in[1] + h;
+        c[0] = in[0] - (rng_u01(r) < 0.5 ? g_ext(r, 16.0) : 0);
+        c[1] = in[1] - (rng_u01(r) < 0.5 ? g_ext(r, 16.0) : 0);
+        c[2] = in[2] + (rng_u01(r) < 0.5 ? g_ext(r, 16.0) : 0);
+        c[3] = in[3] + (rng_u01(r) < 0.5 ? g_ext(r, 16.0) : 0);
+        /* (inside an already disjoint subtree every box is empty anyway) */
+        if (rng_u01(r) < b->p_disjoint && rg[0] >= 0) {
+            const int64_t shift = (int64_t)(8192 * INSET_G);
+            c[0] -= shift, c[2] -= shift, in[0] -= shift, in[2] -= shift;
+        }
+    }
+    memcpy(inner, in, sizeof in);
+    inset_store(dst, c);
 }
 
 static void draw_box(builder *b, float *dst) {
@@ -154,7 +282,11 @@ static void b_emit(builder *b, uint32_t k) {
     b->kind[i] = k;
     float *dst = b->box + 4 * i;
     dst[0] = dst[1] = dst[2] = dst[3] = 0.0f;
-    if (k == K_LEAF || k == K_BCLIP) {
+    const int inset = b->box_mode == BOX_INSET || b->box_mode == BOX_INSET_ND;
+    int64_t inner[4] = {0, 0, 0, 0};
+    if (inset && (k == K_LEAF || k == K_BCLIP)) {
+        draw_inset(b, k, dst, inner);
+    } else if (k == K_LEAF || k == K_BCLIP) {
         if (b->box_mode == BOX_NESTED && k == K_LEAF) {
             /* BOX_NESTED: leaves keep the independent draw, only clips nest;
                BOX_NESTED_ALL nests leaves too */
@@ -170,6 +302,12 @@ static void b_emit(builder *b, uint32_t k) {
         int64_t below = b->sp > 0 ? b->clipanc[b->sp - 1] : -1;
         b->stk[b->sp] = i;
         b->clipanc[b->sp] = (k == K_BCLIP) ? i : below;
+        if (inset) {
+            if (k == K_BCLIP)
+                memcpy(b->reg + 4 * b->sp, inner, sizeof inner);
+            else
+                inset_region(b, b->reg + 4 * b->sp);
+        }
         b->sp++;
     } else if (k == K_ECLIP || k == K_EBLEND) {
         b->sp--;
@@ -230,7 +368,10 @@ typedef struct { int64_t depth, leaves; } chain_ctx;
 
 static void chain_hook(builder *b, void *vctx) {
     chain_ctx *c = (chain_ctx *)vctx;
+    b->in_chain = 1;
+    b->chain_first = 1;
     for (int64_t j = 0; j < c->depth; ++j) b_emit(b, (j & 1) ? K_BBLEND : K_BCLIP);
+    b->in_chain = 0;
     for (int64_t j = 0; j < c->leaves; ++j) b_emit(b, K_LEAF);
     for (int64_t j = 0; j < c->depth; ++j) b_close(b);
 }
@@ -285,7 +426,10 @@ int tbg_chain_around_walk(uint32_t *kind, float *box, int64_t depth, int64_t n_w
     int64_t n = 2 * depth + n_walk;
     builder b;
     if (b_init(&b, kind, box, n, depth + cap, seed, box_mode)) return -1;
+    b.in_chain = 1;
+    b.chain_first = 1;
     for (int64_t j = 0; j < depth; ++j) b_emit(&b, (j & 1) ? K_BBLEND : K_BCLIP);
+    b.in_chain = 0;
     b_walk(&b, n_walk, cap, NULL, 0, NULL, NULL);
     for (int64_t j = 0; j < depth; ++j) b_close(&b);
     int ok = (b.pos == n && b.sp == 0);

@@ -92,6 +92,7 @@ typedef enum {
 #define TB_DATA_UNBALANCED 0x2u    /* a close with no open, or an open never closed */
 #define TB_DATA_KIND_MISMATCH 0x4u /* END_CLIP closing BEGIN_BLEND or vice versa */
 #define TB_DATA_BAD_OFFSETS 0x8u   /* batched: offsets not 0 = o[0] <= ... <= o[S] = total_n */
+#define TB_DATA_GRAD_RANGE 0x10u   /* backward: a routed upstream gradient with |g| >= 2^31 or NaN */
 
 /* Operation codes for tb_workspace_bytes. */
 #define TB_OP_MATCH 0
@@ -141,8 +142,13 @@ tb_status tb_bbox(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t
  * non-EMPTY output equals the blend's coordinate.  Contributions are summed
  * exactly as 64-bit integers on a 2^-32 grid (each g rounded half-to-even to
  * the grid) and rounded once to fp32, so the result does not depend on
- * summation order.  Precondition: every partial sum is below 2^31 in
- * magnitude.
+ * summation order.  Rounding to the grid makes a contribution with
+ * |g| < 2^-9 inexact and one with |g| <= 2^-33 zero.  A routed g with
+ * |g| >= 2^31 (or NaN) sets TB_DATA_GRAD_RANGE.  The integer sums wrap
+ * modulo 2^64; precondition: each final sum fits in an int64 (the exact
+ * gradient is below 2^31 in magnitude).
+ * The forward's match output is not an argument: the pass recomputes the
+ * pairs together with the attaining indices.
  *   kind, box_in [n]  as for tb_bbox                         (in)
  *   grad_out     [n]  tb_box upstream gradient               (in)
  *   grad_in      [n]  tb_box gradient w.r.t. box_in          (out)

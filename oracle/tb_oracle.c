@@ -245,8 +245,11 @@ uint32_t tbo_bbox_f64(const uint32_t *kind, const double *box, int64_t n, double
  *  - Rows whose out is EMPTY route nothing.
  * grad_in[src][c] accumulates q(g) = round-half-even(g * 2^32) as an exact
  * 64-bit integer (order cannot change an integer sum), and is then rounded
- * once to fp32: grad_in = RNE_fp32(sum) * 2^-32.  Precondition: every
- * partial sum stays below 2^31 in magnitude.  Rows never attained get 0.
+ * once to fp32: grad_in = RNE_fp32(sum) * 2^-32.  q(g) rounds every g to a
+ * multiple of 2^-32, so a contribution with |g| < 2^-9 (fewer than 24
+ * significant bits left on that grid) is not exact, and |g| <= 2^-33 counts
+ * as 0.  Sums wrap modulo 2^64; precondition: the final sum fits in an
+ * int64 (|sum of g| < 2^31).  Rows never attained get 0.
  *
  * Written as the definition: every leaf/clip row walks its whole ancestor
  * chain, every blend row visits every row of its slice.
@@ -304,11 +307,17 @@ uint32_t tbo_sources(const uint32_t *kind, const float *box, int64_t n, int64_t 
     return status;
 }
 
+/* q(g) is defined for |g| < 2^31 only (g * 2^32 must fit in an int64); a
+   routed coordinate whose upstream gradient lies outside that range, or is
+   NaN, sets this status bit instead of contributing. */
+enum { ST_GRAD_RANGE = 16u };
+
 uint32_t tbo_backward(const uint32_t *kind, const float *box, const float *grad_out, int64_t n,
                       float *grad_in) {
     size_t m = (size_t)(n > 0 ? n : 1);
     int64_t *src = (int64_t *)malloc(sizeof(int64_t) * 4 * m);
-    int64_t *acc = (int64_t *)calloc(4 * m, sizeof(int64_t));
+    /* sums wrap modulo 2^64 (unsigned), so only the final sum must fit */
+    uint64_t *acc = (uint64_t *)calloc(4 * m, sizeof(uint64_t));
     if (!src || !acc) return 0xFFFFFFFFu;
     uint32_t status = tbo_sources(kind, box, n, src);
     if (!status) {
@@ -316,11 +325,16 @@ uint32_t tbo_backward(const uint32_t *kind, const float *box, const float *grad_
             for (int c = 0; c < 4; ++c) {
                 int64_t s = src[4 * o + c];
                 if (s < 0) continue;
-                double g = (double)grad_out[4 * o + c] * 4294967296.0; /* exact scaling */
-                acc[4 * s + c] += (int64_t)llrint(g);
+                float gf = grad_out[4 * o + c];
+                if (!(fabsf(gf) < 2147483648.0f)) {
+                    status |= ST_GRAD_RANGE;
+                    continue;
+                }
+                double g = (double)gf * 4294967296.0; /* exact scaling */
+                acc[4 * s + c] += (uint64_t)llrint(g);
             }
     }
-    for (int64_t i = 0; i < 4 * n; ++i) grad_in[i] = (float)acc[i] * 0x1p-32f;
+    for (int64_t i = 0; i < 4 * n; ++i) grad_in[i] = (float)(int64_t)acc[i] * 0x1p-32f;
     free(src), free(acc);
     return status;
 }

@@ -20,7 +20,10 @@ import torch
 from ._build import LIB, build  # noqa: F401
 
 LEAF, BEGIN_CLIP, END_CLIP, BEGIN_BLEND, END_BLEND, OTHER = range(6)
-DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS = 1, 2, 4, 8
+DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS, DATA_GRAD_RANGE = 1, 2, 4, 8, 16
+_DATA_NAMES = {DATA_BAD_KIND: "BAD_KIND", DATA_UNBALANCED: "UNBALANCED",
+               DATA_KIND_MISMATCH: "KIND_MISMATCH", DATA_BAD_OFFSETS: "BAD_OFFSETS",
+               DATA_GRAD_RANGE: "GRAD_RANGE"}
 OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE, OP_BBOX_STREAM = range(6)
 
 _lib = None
@@ -55,23 +58,50 @@ def lib():
     return _lib
 
 
+# Workspaces are cached per (device, stream): calls on one stream are ordered,
+# so they may share one; calls on different streams get different buffers.
+# A buffer used while a HIP graph is being captured is written by every
+# replay of that graph, so it is never freed or handed to another stream:
+# it moves to _ws_pinned when the cache replaces it.
 _ws_cache = {}
+_ws_pinned = []
 
 
 def workspace(op, n, num_scenes=1, device=None):
-    """A device workspace of at least tb_workspace_bytes(op, n, S) bytes
-    (cached per device; grown on demand)."""
+    """A device workspace of at least tb_workspace_bytes(op, n, S) bytes for
+    the current stream (cached per device and stream; grown on demand)."""
     need = lib().tb_workspace_bytes(op, n, num_scenes)
     if need == 0:
         raise TreeBBoxError(f"invalid size for op {op}: n={n}, scenes={num_scenes}")
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-    buf = _ws_cache.get(dev)
-    if buf is None or buf.numel() < need:
-        buf = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-        _ws_cache[dev] = buf
+    key = (dev, torch.cuda.current_stream(dev).cuda_stream)
+    capturing = torch.cuda.is_current_stream_capturing()
+    ent = _ws_cache.get(key)
+    if ent is None or ent[0].numel() < need:
+        if ent is not None and ent[1]:
+            _ws_pinned.append(ent[0])
+        ent = [torch.empty(need + 256, dtype=torch.uint8, device=dev), False]
+        _ws_cache[key] = ent
+    ent[1] = ent[1] or capturing
+    buf = ent[0]
     ptr = buf.data_ptr()
     pad = (-ptr) % 256
     return ptr + pad, buf.numel() - pad
+
+
+def status_bits(word):
+    """Names of the TB_DATA_* bits set in a status word."""
+    return [name for bit, name in _DATA_NAMES.items() if int(word) & bit]
+
+
+def check_status(status, what="tb call"):
+    """Raise TreeBBoxError if any status word is non-zero (synchronises)."""
+    words = status.cpu().view(torch.int32).tolist()
+    bad = [(i, w) for i, w in enumerate(words) if w != 0]
+    if bad:
+        i, w = bad[0]
+        raise TreeBBoxError(f"{what}: data error {'|'.join(status_bits(w))} (status word {i} = {w:#x}"
+                            f"; {len(bad)} word(s) non-zero)")
 
 
 def _ptr(t):
@@ -214,24 +244,38 @@ def tb_bbox_stream(tag, box, match=True, out=None, status=None):
 
 
 class TreeBBoxFn(torch.autograd.Function):
-    """box_out = TreeBBoxFn.apply(kind, box); match is returned non-differentiable."""
+    """(box_out, match, status) = TreeBBoxFn.apply(kind, box, check).
+
+    match and status are non-differentiable.  With check=True the forward
+    raises TreeBBoxError on a non-zero status word (malformed scene), and the
+    backward raises on a non-zero status of its own pass (e.g. an upstream
+    gradient out of range); each check synchronises the stream.  With
+    check=False the status words are only returned, and reading them is the
+    caller's job."""
 
     @staticmethod
-    def forward(ctx, kind, box):
+    def forward(ctx, kind, box, check=True):
         out, match, status = tb_bbox(kind, box)
+        if check:
+            check_status(status, "tb_bbox")
         ctx.save_for_backward(kind, box)
+        ctx.check = check
         ctx.mark_non_differentiable(match, status)
         return out, match, status
 
     @staticmethod
     def backward(ctx, g_out, _g_match, _g_status):
         kind, box = ctx.saved_tensors
-        gin, _ = tb_bbox_backward(kind, box, g_out.contiguous())
-        return None, gin
+        gin, status = tb_bbox_backward(kind, box, g_out.contiguous())
+        if ctx.check:
+            check_status(status, "tb_bbox_backward")
+        return None, gin, None
 
 
-def bbox(kind, box):
-    out, _, _ = TreeBBoxFn.apply(kind, box)
+def bbox(kind, box, check=True):
+    """Node boxes through TreeBBoxFn (autograd-aware); raises on malformed
+    input unless check=False."""
+    out, _, _ = TreeBBoxFn.apply(kind, box, check)
     return out
 
 

@@ -419,14 +419,16 @@ __device__ __forceinline__ int64_t scene_of(const int64_t *off, int64_t S, int64
 }
 
 // Scene starts inside [g0, g0+KK) as a bit mask (bit j: element g0+j starts a
-// scene).  Without offsets the only start is element 0.
+// scene).  Without offsets the only start is element 0.  Only o[0..S-1] are
+// scene starts, and only those below n: the end sentinel o[S] = n (and the
+// start of an empty scene at the end) is no element, so it resets nothing.
 template <int KK = K>
-__device__ __forceinline__ uint32_t reset_mask(const int64_t *off, int64_t S, int64_t g0) {
+__device__ __forceinline__ uint32_t reset_mask(const int64_t *off, int64_t S, int64_t n, int64_t g0) {
     if (!off) return g0 == 0 ? 1u : 0u;
     uint32_t r = 0;
-    for (int64_t s = lower_bound64(off, S + 1, g0); s <= S; ++s) {
+    for (int64_t s = lower_bound64(off, S, g0); s < S; ++s) {
         int64_t o = off[s];
-        if (o >= g0 + KK) break;
+        if (o >= g0 + KK || o >= n) break;
         if (o >= g0) r |= 1u << (o - g0);
     }
     return r;

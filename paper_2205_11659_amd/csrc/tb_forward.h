@@ -13,7 +13,7 @@ struct FwdLayout {
     int levels;
     size_t pinfo, part, mtree, bagg, crbase, crtot, jptr0, jptr1, jval0, jval1;
     size_t U_idx, U_cum, U_suf, cr_slot, cr_c, cr_pre;
-    size_t runs, rhead, ptot, upre, usuf, sp, spb, status, acc, selfm;
+    size_t runs, rhead, ptot, upre, usuf, sp, spb, status, offflag, acc, selfm;
     size_t total;
 };
 

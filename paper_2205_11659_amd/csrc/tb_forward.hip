@@ -47,18 +47,27 @@
 namespace tb {
 
 // ------------------------------------------------------------------ utils
-__global__ void k_zero_u32(uint32_t *p, int64_t cnt) {
+// clears the status words and the offsets flag word
+__global__ void k_zero_status(uint32_t *status, int64_t cnt, uint32_t *flagw) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) p[i] = 0u;
+    if (i < cnt) status[i] = 0u;
+    if (i == 0) *flagw = 0u;
 }
 
-// offsets must satisfy 0 = o[0] <= o[1] <= ... <= o[S] = n
-__global__ void k_check_offsets(const int64_t *off, int64_t S, int64_t n, uint32_t *status) {
+// offsets must satisfy 0 = o[0] <= o[1] <= ... <= o[S] = n.  A violation
+// anywhere makes every scene's status BAD_OFFSETS: the checking threads raise
+// one flag word (zeroed with the status words), then k_offsets_flag copies
+// it into all S words, so the cost stays O(S) however many offsets are bad.
+__global__ void k_check_offsets(const int64_t *off, int64_t S, int64_t n, uint32_t *flagw) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s > S) return;
     bool bad = (s == 0 && off[0] != 0) || (s == S && off[S] != n) || (s < S && off[s] > off[s + 1]);
-    if (bad)
-        for (int64_t q = 0; q < S; ++q) atomicOr(status + q, ST_BAD_OFF);
+    if (bad) *flagw = 1u;  // every writer stores the same value
+}
+
+__global__ void k_offsets_flag(const uint32_t *flagw, int64_t S, uint32_t *status) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S && *flagw) status[s] |= ST_BAD_OFF;  // one thread per word: no atomics needed
 }
 
 // ---------------------------------------------------------------- k_reduce
@@ -94,7 +103,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
 #pragma unroll
     for (int j = 0; j < KK; ++j)
         ks[j] = ks[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(ks[j]) : ks[j];
-    const uint32_t rm = reset_mask<KK>(off, S, g0);
+    const uint32_t rm = reset_mask<KK>(off, S, n, g0);
     const Walk wk = walk_kinds<KK>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
     V bxs[KK];
@@ -581,7 +590,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
     for (int j = 0; j < KK; ++j) ks[j] = kr[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(kr[j]) : kr[j];
-    const uint32_t rm = reset_mask<KK>(off, S, g0);
+    const uint32_t rm = reset_mask<KK>(off, S, n, g0);
     __syncthreads();
 
     // ---- gather the incoming levels [preM, dP] (issued now, stored later)
@@ -1176,13 +1185,20 @@ struct SinkAff {
 // Backward: each coordinate of a non-EMPTY output row routes q(g) to its
 // attaining input element.  A row's own coordinates are flagged in a
 // per-row mask (no atomics); every other route is an exact 64-bit atomic add.
+// q(g) = g * 2^32 rounded half-to-even to an integer, defined for |g| < 2^31;
+// a routed g outside that range (or NaN) raises GRAD_RANGE instead.
+constexpr uint32_t ST_GRAD_RANGE = 16u;
+__device__ __forceinline__ bool grad_in_range(float g) { return fabsf(g) < 2147483648.0f; }
+
 struct SinkGrad {
     const float4 *g;
     unsigned long long *acc;  // [n][4] two's-complement sums on the 2^-32 grid
     uint8_t *selfm;           // [n] bit c: row i routes coordinate c to itself
     int64_t n;
+    uint32_t *status;
     __device__ __forceinline__ void emit(int64_t i, const BoxS &v) const {
         uint32_t m = 0;
+        bool bad = false;
         if (v.x0 < v.x1 && v.y0 < v.y1) {
             const float4 gv = g[i];
             const float gc[4] = {gv.x, gv.y, gv.z, gv.w};
@@ -1191,19 +1207,22 @@ struct SinkGrad {
             for (int c = 0; c < 4; ++c) {
                 const int64_t s = sc[c];
                 if (s < 0 || s >= n) continue;
+                bad |= !grad_in_range(gc[c]);
                 if (s == i) {
                     m |= 1u << c;
-                } else if (gc[c] != 0.0f) {
+                } else if (gc[c] != 0.0f && grad_in_range(gc[c])) {
                     const long long q = __double2ll_rn((double)gc[c] * 4294967296.0);
                     atomicAdd(acc + 4 * s + c, (unsigned long long)q);
                 }
             }
         }
+        if (bad) atomicOr(status, ST_GRAD_RANGE);
         selfm[i] = (uint8_t)m;
     }
 };
 
-// grad_in = RNE_fp32(acc + own q(g)) * 2^-32
+// grad_in = RNE_fp32(acc + own q(g)) * 2^-32; the integer sums wrap modulo
+// 2^64, so only the final sum has to fit in an int64
 __global__ void k_grad_final(const float4 *__restrict__ g, const unsigned long long *__restrict__ acc,
                              const uint8_t *__restrict__ selfm, float4 *__restrict__ gin, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1214,9 +1233,10 @@ __global__ void k_grad_final(const float4 *__restrict__ g, const unsigned long l
     float r[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        long long s = (long long)acc[4 * i + c];
-        if ((m >> c) & 1u) s += __double2ll_rn((double)gc[c] * 4294967296.0);
-        r[c] = __ll2float_rn(s) * 0x1p-32f;
+        unsigned long long s = acc[4 * i + c];
+        if (((m >> c) & 1u) && grad_in_range(gc[c]))
+            s += (unsigned long long)__double2ll_rn((double)gc[c] * 4294967296.0);
+        r[c] = __ll2float_rn((long long)s) * 0x1p-32f;
     }
     gin[i] = make_float4(r[0], r[1], r[2], r[3]);
 }
@@ -1454,6 +1474,7 @@ FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad) {
     L.sp = take(vbytes * nb * lv);
     L.spb = take(vbytes * M * UBL);
     L.status = take(sizeof(uint32_t) * (S > 0 ? S : 1));
+    L.offflag = take(sizeof(uint32_t));
     if (grad) {
         L.acc = take(sizeof(unsigned long long) * 4 * (n > 0 ? n : 1));
         L.selfm = take(n > 0 ? n : 1);
@@ -1548,8 +1569,12 @@ static uint32_t *prep_status(char *w, const FwdLayout &L, const int64_t *off, in
                              int64_t n, uint32_t *status, hipStream_t st) {
     const int64_t nstat = off ? S : 1;
     if (!status) status = (uint32_t *)(w + L.status);
-    k_zero_u32<<<(unsigned)((nstat + 255) / 256), 256, 0, st>>>(status, nstat);
-    if (off) k_check_offsets<<<(unsigned)((S + 1 + 255) / 256), 256, 0, st>>>(off, S, n, status);
+    uint32_t *flagw = (uint32_t *)(w + L.offflag);
+    k_zero_status<<<(unsigned)((nstat + 255) / 256), 256, 0, st>>>(status, nstat, flagw);
+    if (off) {
+        k_check_offsets<<<(unsigned)((S + 1 + 255) / 256), 256, 0, st>>>(off, S, n, flagw);
+        k_offsets_flag<<<(unsigned)((S + 255) / 256), 256, 0, st>>>(flagw, S, status);
+    }
     return status;
 }
 
@@ -1634,7 +1659,7 @@ hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_o
     uint8_t *selfm = (uint8_t *)(w + L.selfm);
     k_zero_u64<<<(unsigned)((4 * n + 255) / 256), 256, 0, st>>>(acc, 4 * n);
     hipError_t e = run_pipeline<true, BoxS, SinkGrad>(kind, box, n, nullptr, 1, nullptr, nullptr,
-                                                      SinkGrad{grad_out, acc, selfm, n}, w, L,
+                                                      SinkGrad{grad_out, acc, selfm, n, status}, w, L,
                                                       status, st);
     if (e != hipSuccess) return e;
     k_grad_final<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(grad_out, acc, selfm, grad_in, n);

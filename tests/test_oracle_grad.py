@@ -202,3 +202,65 @@ def test_finite_differences_fp64():
             assert abs(fd - exact) <= 1e-9 * abs(exact), (e, c, fd, exact)
         done += 1
     assert nonzero > 100
+
+
+def _clip_over_leaves(m):
+    """One BEGIN_CLIP (0,0,10,10) over m leaves that each stick out on every
+    side, so every coordinate of every row is attained by the clip alone."""
+    kind = np.array([1] + [0] * m + [2], np.uint32)
+    box = np.zeros((m + 2, 4), np.float32)
+    box[0] = [0, 0, 10, 10]
+    box[1:m + 1] = [-5, -5, 20, 20]
+    return kind, box
+
+
+def test_tiny_contributions_on_the_grid():
+    """The rule rounds each g to the 2^-32 grid before summing: several
+    |g| < 2^-9 contributions landing on one coordinate give RNE(sum of
+    q32(g)), which is not the correctly rounded exact sum (the reading of
+    the gradient rule: an int64 grid, not the 2^-64 / int128 one)."""
+    m = 9
+    kind, box = _clip_over_leaves(m)
+    tiny = np.array([3e-10, -7e-11, 1.5e-9, 2.0 ** -33, -(2.0 ** -33), 1.5 * 2.0 ** -33,
+                     2.5 * 2.0 ** -33, 1e-12, 2.0 ** -10], np.float32)
+    g = np.zeros((m + 2, 4), np.float32)
+    for c in range(4):
+        g[1:m + 1, c] = np.roll(tiny, c) * (1 if c % 2 == 0 else -1)
+    g[0] = [2.0 ** -20, 0.0, 0.0, 0.0]  # the clip's own row routes to itself
+    g[m + 1] = [0.0, 3e-11, 0.0, -(2.0 ** -12)]  # END_CLIP routes like its BEGIN_CLIP
+    gi, st = oracle.backward(kind, box, g)
+    assert st == 0
+    inexact = 0
+    for c in range(4):
+        contribs = [g[o, c] for o in range(m + 2)]
+        want = rne_f32_of_int(sum(q32(v) for v in contribs)) * np.float32(2.0 ** -32)
+        assert gi[0, c].view(np.uint32) == np.float32(want).view(np.uint32), (c, gi[0, c], want)
+        exact = np.float32(float(sum(Fraction(float(v)) for v in contribs)))
+        inexact += int(exact != gi[0, c])
+    assert inexact >= 2  # the grid rounding really shows
+    assert (gi[1:] == 0).all()
+    # 2^-33 itself rounds to 0 (half to even); 1.5 * 2^-33 and 2.5 * 2^-33 to 2^-32
+    assert q32(np.float32(2.0 ** -33)) == 0 and q32(np.float32(1.5 * 2.0 ** -33)) == 1
+    assert q32(np.float32(2.5 * 2.0 ** -33)) == 1
+
+
+def test_grad_range_status():
+    """A routed |g| >= 2^31 (or NaN) has no q32 and sets GRAD_RANGE (16); a
+    NaN on a coordinate that routes nothing is ignored."""
+    kind, box = _clip_over_leaves(3)
+    g = np.ones((5, 4), np.float32)
+    g[2, 1] = np.float32(3e9)
+    _, st = oracle.backward(kind, box, g)
+    assert st == 16
+    g[2, 1] = np.nan
+    _, st = oracle.backward(kind, box, g)
+    assert st == 16
+    g[2, 1] = np.float32(2.0 ** 31 - 128)  # the largest fp32 below 2^31 is fine
+    _, st = oracle.backward(kind, box, g)
+    assert st == 0
+    kind2 = np.array([1, 0, 2], np.uint32)
+    box2 = np.array([[0, 0, 10, 10], [20, 20, 30, 30], [0, 0, 0, 0]], np.float32)  # leaf clipped EMPTY
+    g2 = np.ones((3, 4), np.float32)
+    g2[1] = np.nan
+    _, st = oracle.backward(kind2, box2, g2)
+    assert st == 0
