@@ -84,7 +84,8 @@ typedef enum {
     TB_ERR_ALIGN = 3,     /* a pointer violates the alignment stated above */
     TB_ERR_WORKSPACE = 4, /* ws_bytes < tb_workspace_bytes(...) */
     TB_ERR_ARG = 5,       /* any other invalid argument */
-    TB_ERR_HIP = 6        /* a HIP launch failed */
+    TB_ERR_HIP = 6,       /* a HIP launch failed */
+    TB_ERR_TOO_LARGE = 7  /* tb_bbox_noalloc: n above TB_NOALLOC_MAX_N */
 } tb_status;
 
 /* Device-side data error bits (OR-ed into the status word). */
@@ -131,6 +132,22 @@ tb_status tb_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm,
 tb_status tb_bbox(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
                   tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
                   void *stream);
+
+/*
+ * tb_bbox without a workspace argument, for callers that cannot allocate one
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same results as tb_bbox, bit for bit.  Intermediates live in
+ * a fixed 64 MiB device array inside the library, one per GPU, held until
+ * the process ends; nothing is allocated by the call.  Every call on a GPU
+ * shares that GPU's array, so calls that overlap on one GPU race: order them
+ * on one stream.  n <= TB_NOALLOC_MAX_N (2^20), else TB_ERR_TOO_LARGE before
+ * any work is enqueued.  The array of the stream's device is used (the
+ * current device for the NULL stream).
+ *   kind, box_in, match, box_out, dev_status  as for tb_bbox
+ */
+#define TB_NOALLOC_MAX_N (1 << 20)
+tb_status tb_bbox_noalloc(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
+                          tb_box *box_out, uint32_t *dev_status, void *stream);
 
 /*
  * Gradient of tb_bbox's box_out with respect to box_in (not in the paper).

@@ -49,8 +49,9 @@ def lib():
         L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
         L.tb_compose.argtypes = [P, P, I64, P, P, SZ, P, P]
         L.tb_bbox_stream.argtypes = [P, P, I64, P, P, P, SZ, P, P]
+        L.tb_bbox_noalloc.argtypes = [P, P, I64, P, P, P, P]
         for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched, L.tb_compose,
-                  L.tb_bbox_stream):
+                  L.tb_bbox_stream, L.tb_bbox_noalloc):
             f.restype = ctypes.c_int
         L.tb_status_str.argtypes = [ctypes.c_int]
         L.tb_status_str.restype = ctypes.c_char_p
@@ -166,6 +167,22 @@ def tb_bbox(kind, box, match=True, out=None, status=None):
     _check(lib().tb_bbox(_ptr(kind), _ptr(box), n, _ptr(m), _ptr(out), ctypes.c_void_p(ws), wsb,
                          _ptr(status), _stream()))
     return out, m, status
+
+
+NOALLOC_MAX_N = 1 << 20
+
+
+def tb_bbox_noalloc(kind, box, match, out, status):
+    """tb_bbox through the library's fixed per-GPU array instead of a
+    workspace: the library allocates nothing, and neither does this wrapper
+    (match, out and status are the caller's preallocated tensors; match may
+    be None).  n <= NOALLOC_MAX_N.  Calls overlapping on one GPU race."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    box = _as_box(box, n)
+    _check(lib().tb_bbox_noalloc(_ptr(kind), _ptr(box), n, _ptr(match), _ptr(out), _ptr(status),
+                                 _stream()))
+    return out, match, status
 
 
 def tb_bbox_batched(kind, box, offsets, match=True):

@@ -120,6 +120,18 @@ tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int6
                                 (hipStream_t)stream));
 }
 
+tb_status tb_bbox_noalloc(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
+                          tb_box *box_out, uint32_t *dev_status, void *stream) {
+    if (n < 0) return TB_ERR_SIZE;
+    if (n > tb::NOALLOC_MAX_N) return TB_ERR_TOO_LARGE;
+    if (!dev_status || (n > 0 && (!kind || !box_in || !box_out))) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (kind && !aligned(kind, 4)) || (box_in && !aligned(box_in, 16)) ||
+        (box_out && !aligned(box_out, 16)) || (match && !aligned(match, 4)))
+        return TB_ERR_ALIGN;
+    return launched(tb::fwd_run_noalloc(kind, (const float4 *)box_in, n, match, (float4 *)box_out,
+                                        dev_status, (hipStream_t)stream));
+}
+
 tb_status tb_bbox_backward(const uint32_t *kind, const tb_box *box_in, const tb_box *grad_out,
                            int64_t n, tb_box *grad_in, void *ws, size_t ws_bytes,
                            uint32_t *dev_status, void *stream) {
@@ -148,6 +160,8 @@ const char *tb_status_str(tb_status s) {
     case TB_ERR_WORKSPACE: return "TB_ERR_WORKSPACE: workspace too small";
     case TB_ERR_ARG: return "TB_ERR_ARG: invalid argument";
     case TB_ERR_HIP: return "TB_ERR_HIP: HIP launch failed";
+    case TB_ERR_TOO_LARGE:
+        return "TB_ERR_TOO_LARGE: n exceeds the no-allocation variant's maximum of 2^20 elements";
     }
     return "unknown tb_status";
 }

@@ -51,6 +51,14 @@ hipError_t stream_run(const uint32_t *tag, const float4 *box, int64_t n, int32_t
 hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_out, int64_t n,
                    float4 *grad_in, void *ws, uint32_t *status, hipStream_t st);
 
+// tb_bbox over a fixed per-device array instead of a caller's workspace
+// (no allocation anywhere).  NOALLOC_MAX_N elements at most: their forward
+// workspace fits in NOALLOC_BYTES.
+constexpr int64_t NOALLOC_MAX_N = (int64_t)1 << 20;
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+hipError_t fwd_run_noalloc(const uint32_t *kind, const float4 *box, int64_t n, int32_t *match,
+                           float4 *out, uint32_t *status, hipStream_t st);
+
 // Events recorded around the main per-partition kernel (nullptr = off).
 extern hipEvent_t g_prof_before, g_prof_after;
 

@@ -41,6 +41,8 @@
 // scene starts).  The draw-object stream front end (k_cmp_count,
 // k_cmp_scan, k_cmp_scatter, k_stream_match) extracts the tree's elements
 // before the pipeline and translates the partners after it.
+#include <mutex>
+
 #include "tb_common.h"
 #include "tb_forward.h"
 
@@ -1590,6 +1592,56 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
                                                 L, status, st);
     return run_pipeline<false, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w, L,
                                              status, st);
+}
+
+// ------------------------------------------------- no-allocation variant
+// A fixed device array stands in for the caller's workspace, for callers that
+// cannot allocate one.  Each GPU holds its own copy for the life of the
+// process; every call on a GPU uses that GPU's copy, so calls that overlap on
+// one GPU race and must be ordered on one stream.  The pipeline clears the
+// only words that must start at zero (status and the offsets flag) itself.
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAXDEV = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAXDEV];  // device address of `scratch`, per device
+
+// The address of the calling device's copy of `scratch`: looked up once per
+// device with that device current (the host-side name of the array is only a
+// stand-in and must never reach a kernel).
+hipError_t scratch_for(hipStream_t st, void **out) {
+    int dev = 0;
+    hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255u)) return hipErrorInvalidValue;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t fwd_run_noalloc(const uint32_t *kind, const float4 *box, int64_t n, int32_t *match,
+                           float4 *out, uint32_t *status, hipStream_t st) {
+    if (fwd_layout(n, 1, sizeof(Box), false).total > NOALLOC_BYTES) return hipErrorInvalidValue;
+    void *ws = nullptr;
+    const hipError_t e = scratch_for(st, &ws);
+    if (e != hipSuccess) return e;
+    return fwd_run(true, kind, box, n, nullptr, 1, match, nullptr, out, ws, status, st);
 }
 
 hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,
