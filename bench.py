@@ -142,6 +142,7 @@ def small_section(reps=100):
     out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     match = torch.empty(n, dtype=torch.int32, device="cuda")
     st = torch.empty(1, dtype=torch.int32, device="cuda")
+    tuned, _ = tb.tune_bbox(kind, box, reps=5)  # untimed: picks the launch variant for this size
     tb.tb_bbox(kind, box, match=match, out=out, status=st)
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
@@ -162,7 +163,8 @@ def small_section(reps=100):
     assert int(st.item()) == 0
     us = a.elapsed_time(b) * 1e3 / reps
     return {"workload": c["name"], "elements": n, "us_per_call": round(us, 2),
-            "gelem_s": round(n / us / 1e3, 3), "timing": f"HIP graph of one call, {reps} replays"}
+            "gelem_s": round(n / us / 1e3, 3), "timing": f"HIP graph of one call, {reps} replays",
+            "autotune": _tune_record(tuned)}
 
 
 def copy_ceiling(reps=10):
@@ -186,6 +188,15 @@ def copy_ceiling(reps=10):
     del src, dst
     return {"gbs": round(nbytes / (ms / 1e3) / 1e9, 1), "bytes_moved": nbytes,
             "bytes_read_per_copy": nbytes // 2, "frac_of_peak": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def _tune_record(t):
+    """The autotuner's choice for a section: variant (elements per thread of
+    the main and the reduce pass, close records per thread of the cross
+    pass) and its median time against the default variant's."""
+    return {"variant": list(t["variant"]), "ms": round(t["ms"], 4),
+            "default_ms": round(t["default_ms"], 4),
+            "gain": round(t["default_ms"] / t["ms"], 4) if t["ms"] > 0 else None}
 
 
 def gpu_clocks():
@@ -235,6 +246,7 @@ def batched_section(steps, warmup, cpu=False):
     kind, box = torch.from_numpy(c["kind"].view(np.int32)).cuda(), torch.from_numpy(c["box"]).cuda()
     off = torch.from_numpy(c["offsets"]).cuda()
     out = {}
+    tuned, _ = tb.tune_bbox_batched(kind, box, off, reps=3)
     ms_b = time_steps(lambda: tb.tb_bbox_batched(kind, box, off), steps, warmup)
     bout, bm, bst = tb.tb_bbox_batched(kind, box, off)
     g = tb.PerSceneGraph(kind, box, c["offsets"])
@@ -246,7 +258,8 @@ def batched_section(steps, warmup, cpu=False):
     out.update({"workload": "batch-2048-ragged", "elements": n, "scenes": len(c["offsets"]) - 1,
                 "batched_ms": round(ms_b, 4), "batched_gelem_s": round(n / ms_b / 1e6, 3),
                 "per_scene_graph_ms": round(ms_g, 4), "per_scene_graph_gelem_s": round(n / ms_g / 1e6, 3),
-                "speedup": round(ms_g / ms_b, 3), "byte_identical": same})
+                "speedup": round(ms_g / ms_b, 3), "byte_identical": same,
+                "autotune": _tune_record(tuned)})
     if cpu:
         out["cpu_baseline_threads"] = oracle_scenes_threads(c["kind"], c["box"], c["offsets"])
     return out
@@ -298,6 +311,7 @@ def match_section(steps, warmup, kind_np=None):
     m = torch.empty(n, dtype=torch.int32, device="cuda")
     pm = torch.empty(n, dtype=torch.int32, device="cuda")
     st = torch.empty(1, dtype=torch.int32, device="cuda")
+    tuned, _ = tb.tune_match(kind, reps=3)
     ms = time_steps(lambda: tb.tb_match(kind, pm=False, match=m, status=st), steps, warmup)
     ms_pm = time_steps(lambda: tb.tb_match(kind, pm=pm, match=m, status=st), steps, warmup)
     torch.cuda.synchronize()
@@ -305,7 +319,7 @@ def match_section(steps, warmup, kind_np=None):
     return {"workload": "scene-128M-chain32M", "elements": n, "ms_per_step": round(ms, 4),
             "gelem_s": round(n / ms / 1e6, 3),
             "hbm_frac_alg": round(8 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "with_pm_ms": round(ms_pm, 4),
+            "with_pm_ms": round(ms_pm, 4), "autotune": _tune_record(tuned),
             "context": "the paper reports 13.5 Gelem/s for matching alone on a Radeon 5700 XT"}
 
 
@@ -377,6 +391,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="time the default launch variant")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
     ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small",
                                        "c1", "copy"],
@@ -410,6 +425,9 @@ def main():
     match = torch.empty(n, dtype=torch.int32, device=dev)
     status = torch.empty(1, dtype=torch.int32, device=dev)
 
+    tuned = None
+    if not args.no_tune:  # untimed: the autotuner picks the launch variant for this size
+        tuned, _ = tb.tune_bbox(kind, box, reps=3)
     for _ in range(args.warmup):
         tb.tb_bbox(kind, box, match=match, out=out, status=status)
     torch.cuda.synchronize()
@@ -460,6 +478,7 @@ def main():
                     "wall_mean": round(ms_step, 4),
                     "timing": "value from the median of per-step HIP events on the call's stream"},
         "path_hbm_frac": round(ALG_BYTES_FWD * n / (med_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "autotune": _tune_record(tuned) if tuned else None,
         "gpu_clocks": {"before": clocks_before, "after": clocks_after},
         "roofline": {"bound": "hbm", "kernel": "k_resolve", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -230,6 +230,54 @@ tb_status tb_bbox_stream(const uint32_t *tag, const tb_box *box_in, int64_t n, i
                          void *stream);
 
 /*
+ * Autotuning.  The paper finds that the best number of elements per thread
+ * depends on the problem size (section "Performance results").  A call's
+ * launch variant is: elements per thread of the main pass and of the
+ * reduce pass (4 or 8 each; the partition stays 1024 elements, so the
+ * workspace does not change) and close records per thread of the
+ * cross-partition pass (2, 4 or 8; matching alone uses 4).  Results never
+ * depend on the variant.  Calls of tb_match, tb_bbox and tb_bbox_batched
+ * use, for their size class ceil(log2 n), the variant chosen for the
+ * current device kind (architecture and compute-unit count), else the
+ * default (4, 4, 4 for boxes; 8, 8, 4 for matching alone).
+ *
+ * tb_tune_*: same arguments as the call they tune, plus `reps`; each
+ * candidate variant runs one warm-up and `reps` timed calls on the caller's
+ * input (outputs overwritten), the fastest median is kept for n's size
+ * class, and the outputs are left as the chosen variant wrote them.  They
+ * synchronise `stream` and create two HIP events.  Optional outputs:
+ * *chosen, and ms[0], ms[1] = the chosen and the default variant's median
+ * milliseconds.  Not for use under graph capture.
+ */
+typedef struct {
+    int32_t resolve_elems; /* elements per thread of the main pass: 4 or 8 */
+    int32_t reduce_elems;  /* elements per thread of the reduce pass: 4 or 8 */
+    int32_t cross_records; /* close records per thread of the cross-partition pass: 2, 4, 8 */
+} tb_variant;
+
+tb_status tb_tune_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                        size_t ws_bytes, uint32_t *dev_status, void *stream, int reps,
+                        tb_variant *chosen, float *ms);
+tb_status tb_tune_bbox(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
+                       tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
+                       void *stream, int reps, tb_variant *chosen, float *ms);
+tb_status tb_tune_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int64_t *offsets,
+                               int64_t num_scenes, int64_t total_n, int32_t *match, tb_box *box_out,
+                               void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream,
+                               int reps, tb_variant *chosen, float *ms);
+/* The variant calls of `op` (TB_OP_MATCH, TB_OP_BBOX, TB_OP_BBOX_BATCHED)
+   on n elements use on the current device; set pins one (NULL: back to the
+   default; TB_ERR_ARG for an invalid variant or op). */
+tb_status tb_variant_get(int op, int64_t n, tb_variant *out);
+tb_status tb_variant_set(int op, int64_t n, const tb_variant *v);
+/* The table of chosen variants as text (one line per device kind, op and
+   size class); load merges a saved table (TB_ERR_ARG if the file cannot be
+   read or is not such a table); clear forgets every choice. */
+tb_status tb_tune_save(const char *path);
+tb_status tb_tune_load(const char *path);
+void tb_tune_clear(void);
+
+/*
  * Profiling hook: when both are non-NULL, later calls record `before` and
  * `after` (hipEvent_t handles created by the caller) on the call's stream
  * immediately around the launch of the main per-partition kernel, so its

@@ -53,6 +53,19 @@ def lib():
         for f in (L.tb_match, L.tb_bbox, L.tb_bbox_backward, L.tb_bbox_batched, L.tb_compose,
                   L.tb_bbox_stream, L.tb_bbox_noalloc):
             f.restype = ctypes.c_int
+        I32 = ctypes.c_int
+        L.tb_tune_match.argtypes = [P, I64, P, P, P, SZ, P, P, I32, P, P]
+        L.tb_tune_bbox.argtypes = [P, P, I64, P, P, P, SZ, P, P, I32, P, P]
+        L.tb_tune_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P, I32, P, P]
+        L.tb_variant_get.argtypes = [I32, I64, P]
+        L.tb_variant_set.argtypes = [I32, I64, P]
+        L.tb_tune_save.argtypes = [ctypes.c_char_p]
+        L.tb_tune_load.argtypes = [ctypes.c_char_p]
+        for f in (L.tb_tune_match, L.tb_tune_bbox, L.tb_tune_bbox_batched, L.tb_variant_get,
+                  L.tb_variant_set, L.tb_tune_save, L.tb_tune_load):
+            f.restype = I32
+        L.tb_tune_clear.argtypes = []
+        L.tb_tune_clear.restype = None
         L.tb_status_str.argtypes = [ctypes.c_int]
         L.tb_status_str.restype = ctypes.c_char_p
         _lib = L
@@ -258,6 +271,102 @@ def tb_bbox_stream(tag, box, match=True, out=None, status=None):
     _check(lib().tb_bbox_stream(_ptr(tag), _ptr(box), n, _ptr(m), _ptr(out), ctypes.c_void_p(ws),
                                 wsb, _ptr(status), _stream()))
     return out, m, status
+
+
+# ---------------------------------------------------------------- tuning
+class Variant(ctypes.Structure):
+    """Launch variant: elements per thread of the main and the reduce pass,
+    close records per thread of the cross-partition pass."""
+    _fields_ = [("resolve_elems", ctypes.c_int32), ("reduce_elems", ctypes.c_int32),
+                ("cross_records", ctypes.c_int32)]
+
+    def astuple(self):
+        return (self.resolve_elems, self.reduce_elems, self.cross_records)
+
+
+def variant_get(op, n):
+    v = Variant()
+    _check(lib().tb_variant_get(op, n, ctypes.byref(v)))
+    return v.astuple()
+
+
+def variant_set(op, n, v):
+    """Pin the variant (a 3-tuple) for n's size class; None restores the default."""
+    if v is None:
+        _check(lib().tb_variant_set(op, n, None))
+    else:
+        _check(lib().tb_variant_set(op, n, ctypes.byref(Variant(*v))))
+
+
+def tune_save(path):
+    _check(lib().tb_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    _check(lib().tb_tune_load(os.fsencode(path)))
+
+
+def tune_clear():
+    lib().tb_tune_clear()
+
+
+def _tuned(rc, v, ms):
+    _check(rc)
+    return {"variant": v.astuple(), "ms": float(ms[0]), "default_ms": float(ms[1])}
+
+
+def tune_bbox(kind, box, reps=3):
+    """Time every tb_bbox variant on this input, keep the fastest for its
+    size class; returns {variant, ms, default_ms} and the call's outputs."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    box = _as_box(box, n)
+    dev = kind.device
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    m = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    ws, wsb = workspace(OP_BBOX, n, 1, dev)
+    v, ms = Variant(), (ctypes.c_float * 2)()
+    rc = lib().tb_tune_bbox(_ptr(kind), _ptr(box), n, _ptr(m), _ptr(out), ctypes.c_void_p(ws), wsb,
+                            _ptr(status), _stream(), reps, ctypes.byref(v), ms)
+    return _tuned(rc, v, ms), (out, m, status)
+
+
+def tune_bbox_batched(kind, box, offsets, reps=3):
+    kind = _as_kind(kind)
+    n = kind.numel()
+    box = _as_box(box, n)
+    offsets = offsets.contiguous()
+    S = offsets.numel() - 1
+    dev = kind.device
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    m = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    ws, wsb = workspace(OP_BBOX_BATCHED, n, S, dev)
+    v, ms = Variant(), (ctypes.c_float * 2)()
+    rc = lib().tb_tune_bbox_batched(_ptr(kind), _ptr(box), _ptr(offsets), S, n, _ptr(m), _ptr(out),
+                                    ctypes.c_void_p(ws), wsb, _ptr(status), _stream(), reps,
+                                    ctypes.byref(v), ms)
+    return _tuned(rc, v, ms), (out, m, status)
+
+
+def tune_match(kind, reps=3):
+    kind = _as_kind(kind)
+    n = kind.numel()
+    dev = kind.device
+    m = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    ws, wsb = workspace(OP_MATCH, n, 1, dev)
+    v, ms = Variant(), (ctypes.c_float * 2)()
+    rc = lib().tb_tune_match(_ptr(kind), n, _ptr(m), None, ctypes.c_void_p(ws), wsb, _ptr(status),
+                             _stream(), reps, ctypes.byref(v), ms)
+    return _tuned(rc, v, ms), (m, status)
+
+
+def candidates(op):
+    """Every launch variant the tuner tries for `op`."""
+    boxes = op != OP_MATCH
+    return [(kr, kd, cu) for kr in (4, 8) for kd in (4, 8) for cu in (2, 4, 8) if boxes or cu == 4]
 
 
 class TreeBBoxFn(torch.autograd.Function):

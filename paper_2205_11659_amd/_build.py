@@ -5,7 +5,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtreebbox.so")
-SOURCES = ["csrc/tb_forward.hip", "csrc/tb_api.cpp"]
+SOURCES = ["csrc/tb_forward.hip", "csrc/tb_api.cpp", "csrc/tb_tune.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # never let the compiler form packed fp32 ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

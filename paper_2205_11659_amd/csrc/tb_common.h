@@ -529,26 +529,26 @@ __device__ __forceinline__ int mintree_node(const int *mt, int x) {
     return min(min(mt[4], mt[5]), min(mt[6], mt[7]));
 }
 
-// The wave levels of a union tree of boxes over the W threads: leaves at
-// W + t, internal nodes down to one node per wave (indices NWAVE..2*NWAVE-1),
+// The wave levels of a union tree of boxes over the WW threads: leaves at
+// WW + t, internal nodes down to one node per wave (indices WW/64..WW/32-1),
 // and EMPTY at index 0.  No barrier; nodes above the wave level are not built.
-template <class V>
+template <class V, int WW = W>
 __device__ __forceinline__ void uniontree_wave(V *ut, V v) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
     if (t == 0) ut[0] = Pay<V>::empty();  // the "no node" sentinel of uniontree_inner
-    ut[W + t] = v;
+    ut[WW + t] = v;
     v = unite(v, dmov<dpp::SHR1>(v, v));
-    if ((lane & 1) == 1) ut[(W + t) >> 1] = v;
+    if ((lane & 1) == 1) ut[(WW + t) >> 1] = v;
     v = unite(v, dmov<dpp::SHR2>(v, v));
-    if ((lane & 3) == 3) ut[(W + t) >> 2] = v;
+    if ((lane & 3) == 3) ut[(WW + t) >> 2] = v;
     v = unite(v, dmov<dpp::SHR4>(v, v));
-    if ((lane & 7) == 7) ut[(W + t) >> 3] = v;
+    if ((lane & 7) == 7) ut[(WW + t) >> 3] = v;
     v = unite(v, dmov<dpp::SHR8>(v, v));
-    if ((lane & 15) == 15) ut[(W + t) >> 4] = v;
+    if ((lane & 15) == 15) ut[(WW + t) >> 4] = v;
     v = unite(v, dmov<dpp::BC15, 0xA>(v, v));
-    if ((lane & 31) == 31) ut[(W + t) >> 5] = v;
+    if ((lane & 31) == 31) ut[(WW + t) >> 5] = v;
     v = unite(v, dmov<dpp::BC31, 0xC>(v, v));
-    if (lane == 63) ut[(W + t) >> 6] = v;
+    if (lane == 63) ut[(WW + t) >> 6] = v;
 }
 
 // rightmost leaf s < t with leaf value < v, or -1
@@ -567,14 +567,15 @@ __device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int64_t v
 }
 
 // Union over leaves [lo, hi] of a tree built by uniontree_wave, for
-// 1 <= lo and hi <= W-2 (EMPTY if lo > hi).  Such a range never covers a
-// node above the wave level, so seven levels suffice.  Straight-line: every
-// LDS read is issued before the first is used; a level that contributes
-// nothing reads node 0, which uniontree_wave sets to EMPTY.
-template <class V>
+// 1 <= lo and hi <= WW-2 (EMPTY if lo > hi).  Such a range never covers a
+// node above the wave level (at most four waves), so seven levels suffice.
+// Straight-line: every LDS read is issued before the first is used; a level
+// that contributes nothing reads node 0, which uniontree_wave sets to EMPTY.
+template <class V, int WW = W>
 __device__ __forceinline__ V uniontree_inner(const V *ut, int lo, int hi) {
+    static_assert(WW / WAVE <= 4, "ranges inside at most four waves");
     V r = Pay<V>::empty();
-    int l = lo + W, h = hi + W + 1;
+    int l = lo + WW, h = hi + WW + 1;
 #pragma unroll
     for (int lev = 0; lev < 7; ++lev) {
         const bool go = l < h;

@@ -5,6 +5,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 namespace tb {
 
 // Byte offsets of the forward pipeline's arrays inside the caller's workspace.
@@ -21,11 +24,28 @@ struct FwdLayout {
 // accumulators.
 FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad);
 
+// Launch shape of one forward call: elements per thread of the main pass
+// (kr) and of the reduce pass (kd), 4 or 8, and close records per thread of
+// the cross-partition pass (cu: 2, 4 or 8).  Partitions stay T elements, so
+// the workspace does not depend on the variant.
+struct Variant {
+    int kr = 0, kd = 0, cu = 0;
+};
+inline bool variant_ok(const Variant &v) {
+    return (v.kr == 4 || v.kr == 8) && (v.kd == 4 || v.kd == 8) && (v.cu == 2 || v.cu == 4 || v.cu == 8);
+}
+inline Variant default_variant(bool boxes) {
+    // matching alone needs few registers: 8 elements per thread halve the
+    // per-thread share of the partition-level steps
+    return boxes ? Variant{4, 4, 4} : Variant{8, 8, 4};
+}
+
 // Enqueue the forward pipeline.  boxes=false computes matching only.
 // off == nullptr means one scene.  status may be nullptr (workspace word).
+// An invalid variant means the default one.
 hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t n,
                    const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
-                   void *ws, uint32_t *status, hipStream_t st);
+                   void *ws, uint32_t *status, hipStream_t st, Variant var);
 
 // Transform composition down the tree: xf and out hold 24-byte rows
 // [a b c d e f] (uint32, 8-byte aligned).
@@ -58,6 +78,20 @@ constexpr int64_t NOALLOC_MAX_N = (int64_t)1 << 20;
 constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
 hipError_t fwd_run_noalloc(const uint32_t *kind, const float4 *box, int64_t n, int32_t *match,
                            float4 *out, uint32_t *status, hipStream_t st);
+
+// Autotuner (tb_tune.cpp): the variant that calls of `op` on n elements use
+// on the current device (the default until tuned or set), and the timing of
+// every candidate on a caller's input.  `call` runs one whole forward call
+// with the given variant on the stream.
+Variant variant_for(int op, int64_t n, bool boxes);
+void variant_set(int op, int64_t n, const Variant *v);  // nullptr: back to the default
+std::vector<Variant> candidates(bool boxes);
+hipError_t tune(int op, int64_t n, bool boxes, int reps, hipStream_t st,
+                const std::function<hipError_t(Variant)> &call, Variant *chosen, float *best_ms,
+                float *default_ms);
+bool tune_save(const char *path);
+bool tune_load(const char *path);
+void tune_clear();
 
 // Events recorded around the main per-partition kernel (nullptr = off).
 extern hipEvent_t g_prof_before, g_prof_after;

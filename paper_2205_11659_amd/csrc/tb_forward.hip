@@ -42,6 +42,7 @@
 // k_cmp_scan, k_cmp_scatter, k_stream_match) extracts the tree's elements
 // before the pipeline and translates the partners after it.
 #include <mutex>
+#include <type_traits>
 
 #include "tb_common.h"
 #include "tb_forward.h"
@@ -512,17 +513,26 @@ template <bool BOXES, class V, int KK>
 struct ResolveSmem {
     static constexpr int WW = T / KK, NW = WW / WAVE;
     int4 runs[RMAX];
-    // Until the walk ends: the clip context at each thread's base level, and
-    // the incoming levels [preM, dP] (entry x = level preM + x: the open's
-    // index | BLEND_BIT, or -1 for the root).  Afterwards: the union tree
-    // over threads.
+    // Until the walk ends: the clip context at each thread's base level, the
+    // incoming levels [preM, dP] (entry x = level preM + x: the open's
+    // index | BLEND_BIT, or -1 for the root), the per-thread lookup records,
+    // the min tree and the jumping pointers.  Afterwards: the union tree
+    // over threads, which overlays them all.
     union Early {
         struct {
             V jval[BOXES ? WW : 1];
             int inc_idx[T + 1];
+            // per thread: {lowest level (SENT after a scene start), owner
+            // thread or -1, base level, first cx entry | unmatched-open mask
+            // << 16 | mask of those that are clips << (16 + KK)}; one LDS
+            // read per owner-chain hop
+            int4 tinfo[WW];
+            int mt[2 * WW];
+            int jptr[WW];
         } w;
         V ut[BOXES ? 2 * WW : 1];
     } e;
+    static_assert(KK <= 8 && T < 0xFFFF, "tinfo packs two KK-bit masks above a 16-bit entry");
     // Clip contexts.  Entries [0, aP] belong to the incoming levels; from
     // aP + 1 on come the unmatched opens of each thread in order (thread t's
     // from aP + 1 + tub[t]) with their local clip prefix, which the union
@@ -530,21 +540,12 @@ struct ResolveSmem {
     // its threads' unmatched opens are different elements, so T + 1 entries
     // always suffice.
     V cx[BOXES ? T + 1 : 1];
-    // per thread: {lowest level (SENT after a scene start), owner thread or
-    // -1, base level, first cx entry | unmatched-open mask << 16 | mask of
-    // those that are clips << (16 + KK)}; one LDS read per owner-chain hop
-    int4 tinfo[WW];
-    static_assert(KK <= 8 && T < 0xFFFF, "tinfo packs two KK-bit masks above a 16-bit entry");
-    int mt[2 * WW];
-    int jptr[WW];
-    V jval2[BOXES ? WW : 1];  // second buffer of the cross-wave pointer jumping
-    int jptr2[WW];
     SegU sh_seg[NW];
     V wtot[NW];  // union of each wave's leaves
 };
 
 template <bool BOXES, class V, class SINK, int KK>
-__global__ __launch_bounds__(T / KK) void k_resolve(
+__global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) void k_resolve(
     const uint32_t *__restrict__ kind, const float4 *__restrict__ box, int64_t n,
     const int64_t *__restrict__ off, int64_t S, const int4 *__restrict__ pinfo,
     const int4 *__restrict__ part, const int4 *__restrict__ runs_g,
@@ -555,7 +556,6 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     int32_t *__restrict__ match, int32_t *__restrict__ pm, SINK sink,
     uint32_t *__restrict__ status, const int64_t *__restrict__ n_dyn) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
-    static_assert(!BOXES || KK == K, "the box path's unions are built for K elements per thread");
     __shared__ ResolveSmem<BOXES, V, KK> sm;
     V *ut = sm.e.ut;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
 #pragma unroll
         for (int j = 0; j < KK; ++j)
             if (ks[j] == BCLIP) clipm |= 1u << j;
-        sm.tinfo[t] = make_int4(cm, -1, base, (int)((uint32_t)ub | (wk.umask << 16) | ((clipm & wk.umask) << (16 + KK))));
+        sm.e.w.tinfo[t] = make_int4(cm, -1, base, (int)((uint32_t)ub | (wk.umask << 16) | ((clipm & wk.umask) << (16 + KK))));
     }
     if (BOXES) {
         V c = Pay<V>::inf();
@@ -654,13 +654,13 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     }
     int wmin0;
     int premin = wave_excl_scan(cm, MinOp{}, INT32_MAX, &wmin0);  // lowest level of earlier lanes
-    mintree_build<WW>(sm.mt, cm);  // its barrier also publishes everything above
+    mintree_build<WW>(sm.e.w.mt, cm);  // its barrier also publishes everything above
 
     // levels at or below `lowtop` are held by no earlier thread of this
     // partition: they come from earlier partitions (the LDS table).
 #pragma unroll
     for (int w = 0; w < NW - 1; ++w)
-        if (w < (t >> 6)) premin = min(premin, sm.mt[NW + w]);  // wave nodes of the min tree
+        if (w < (t >> 6)) premin = min(premin, sm.e.w.mt[NW + w]);  // wave nodes of the min tree
     const int lowtop = min(premin, Dt);
     // lowest level any later thread reaches: an unmatched open of this thread
     // at a level not above it survives the partition
@@ -668,11 +668,11 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     int sufmin = wave_excl_suffix_scan(cm, MinOp{}, INT32_MAX, &wmin1);
 #pragma unroll
     for (int w = 1; w < NW; ++w)
-        if (w > (t >> 6)) sufmin = min(sufmin, sm.mt[NW + w]);
+        if (w > (t >> 6)) sufmin = min(sufmin, sm.e.w.mt[NW + w]);
     // owner links between threads: the entry just below a thread's lowest
     // level belongs to the nearest earlier thread with a smaller lowest level
-    const int tl = wk.rs ? -1 : mintree_prev_less<WW>(sm.mt, t, cm);
-    sm.tinfo[t].y = tl;
+    const int tl = wk.rs ? -1 : mintree_prev_less<WW>(sm.e.w.mt, t, cm);
+    sm.e.w.tinfo[t].y = tl;
 
     // ---- clip context at each thread's base level: pointer jumping along
     // owner threads, first inside the wave with shuffles, then across waves.
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
         if (!wk.rs && pre_m > 0) {
             const int s = tl;
             if (s >= 0) {
-                const int4 ti = sm.tinfo[s];
+                const int4 ti = sm.e.w.tinfo[s];
                 const int jj = pre_m - ti.z - 1;
                 const uint32_t um = ((uint32_t)ti.w >> 16) & ((1u << KK) - 1u);
                 const int e = (ti.w & 0xFFFF) + (int)jj;
@@ -705,21 +705,21 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
                 ptr = pp;
             }
         }
-        // Across waves every pointer now leaves its wave, so two doubling
-        // rounds (double-buffered) reach the partition's base for 4 waves.
-        static_assert(NW <= 4, "two doubling rounds cover at most four waves");
+        // Across waves every pointer now leaves its wave, so a chain has at
+        // most NW - 1 more hops: follow it through the published values
+        // (each hop's value is fixed, so hops compose, owner first).
         sm.e.w.jval[t] = v;
-        sm.jptr[t] = ptr;
+        sm.e.w.jptr[t] = ptr;
         __syncthreads();  // also publishes tlink
-        if (ptr >= 0) {
-            v = isect(sm.e.w.jval[ptr], v);
-            ptr = sm.jptr[ptr];
+#pragma unroll
+        for (int h = 0; h < NW - 1; ++h) {
+            if (ptr >= 0) {
+                v = isect(sm.e.w.jval[ptr], v);
+                ptr = sm.e.w.jptr[ptr];
+            }
         }
-        sm.jval2[t] = v;
-        sm.jptr2[t] = ptr;
-        __syncthreads();
-        if (ptr >= 0) v = isect(sm.jval2[ptr], v);
-        sm.e.w.jval[t] = v;  // every read of the first buffer happened before the barrier
+        __syncthreads();  // every read of the published values is done
+        sm.e.w.jval[t] = v;
         __syncthreads();
     } else {
         __syncthreads();  // publishes tlink
@@ -797,10 +797,10 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
                     }
                 }
             } else if (dep > lowtop) {
-                int4 ti = sm.tinfo[own_s >= 0 ? own_s : 0];
+                int4 ti = sm.e.w.tinfo[own_s >= 0 ? own_s : 0];
                 while (own_s >= 0 && ti.x >= dep) {
                     own_s = ti.y;
-                    if (own_s >= 0) ti = sm.tinfo[own_s];
+                    if (own_s >= 0) ti = sm.e.w.tinfo[own_s];
                 }
                 const int s = own_s;
                 if (s >= 0) {
@@ -931,7 +931,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
     V wsuf_dummy;
     const V wsuf = wave_excl_suffix_scan(ttot, UniteOp{}, Pay<V>::empty(), &wsuf_dummy);
     __syncthreads();  // the walk's reads of the early tables and cx are done
-    uniontree_wave(ut, ttot);
+    uniontree_wave<V, WW>(ut, ttot);
     if (lane == 0) sm.wtot[wid] = wtot_u;
     {  // suffix unions after each of this thread's unmatched opens
         V suf = Pay<V>::empty();
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(T / KK) void k_resolve(
             if (q < j && ((leafm >> q) & 1u)) pre = unite(pre, res[q]);
         }
         const int s = (int)(w & 0x1FFu) - 1, pos = (int)((w >> 9) & 7u), ent = (int)(w >> 12);
-        const V u = unite(unite(sm.cx[ent], uniontree_inner(ut, s + 1, t - 1)), pre);
+        const V u = unite(unite(sm.cx[ent], uniontree_inner<V, WW>(ut, s + 1, t - 1)), pre);
         sink.emit(g0 + j, u);
         sink.emit(p0 + (uint32_t)s * KK + pos, u);
     }
@@ -1059,7 +1059,7 @@ __global__ __launch_bounds__(1024) void k_usparse(void *__restrict__ sp, int64_t
     }
 }
 
-template <class V, class SINK>
+template <class V, class SINK, int U>
 __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int64_t n,
                                              const int64_t *__restrict__ off, int64_t S,
                                              const int32_t *__restrict__ U_idx,
@@ -1084,7 +1084,6 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
     // workgroup takes contiguous chunks of U*W records, U per thread; after
     // the records themselves every load is issued at once (unused lanes read
     // entry 0 and discard it).
-    constexpr int U = sizeof(V) <= 16 ? 4 : 2;
     const int64_t total = min((int64_t)*crtot, n);  // at most one record per element
     for (int64_t c0 = (int64_t)blockIdx.x * (U * W); c0 < total; c0 += (int64_t)gridDim.x * (U * W)) {
         const int64_t r0 = c0 + threadIdx.x;
@@ -1485,11 +1484,26 @@ FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad) {
     return L;
 }
 
+// Launch shapes that a variant may change: only the forward box path
+// (tb_bbox, tb_bbox_batched) and matching alone have more than one; every
+// other payload runs the default.
+template <bool BOXES, class V, class SINK>
+constexpr bool kTunable = !BOXES || (std::is_same<V, Box>::value && std::is_same<SINK, SinkOut>::value);
+
+template <bool BOXES, class V, class SINK, int KD>
+static void launch_reduce(int64_t M, hipStream_t st, const uint32_t *kind, const float4 *box, int64_t n,
+                          const int64_t *off, int64_t S, int4 *pinfo, int32_t *U_idx, void *U_cum,
+                          const int64_t *n_dyn) {
+    k_reduce<BOXES, V, KD><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+}
+
 template <bool BOXES, class V, class SINK>
 static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t n,
                                const int64_t *off, int64_t S, int32_t *match, int32_t *pm,
                                SINK sink, char *w, const FwdLayout &L, uint32_t *status,
-                               hipStream_t st, const int64_t *n_dyn = nullptr) {
+                               hipStream_t st, const int64_t *n_dyn = nullptr,
+                               Variant var = Variant{}) {
+    if (!kTunable<BOXES, V, SINK> || !variant_ok(var)) var = default_variant(BOXES);
     const int64_t M = L.M;
     int4 *pinfo = (int4 *)(w + L.pinfo);
     int4 *part = (int4 *)(w + L.part);
@@ -1498,9 +1512,11 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     int *crtot = (int *)(w + L.crtot);
     int32_t *U_idx = (int32_t *)(w + L.U_idx);
     void *U_cum = w + L.U_cum;
-    constexpr int KD = BOXES ? K : 8;  // elements per thread of the reduce
-    k_reduce<BOXES, V, KD><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum,
-                                                              n_dyn);
+    // elements per thread of the reduce
+    if (var.kd == 8)
+        launch_reduce<BOXES, V, SINK, 8>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+    else
+        launch_reduce<BOXES, V, SINK, 4>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
@@ -1542,13 +1558,22 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     void *ptot = w + L.ptot;
     const bool prof = g_prof_before && g_prof_after;
     if (prof) (void)hipEventRecord(g_prof_before, st);
-    // matching alone needs few registers: 8 elements per thread halves the
-    // per-thread work of the partition-level steps
-    constexpr int KR = BOXES ? K : 8;
-    k_resolve<BOXES, V, SINK, KR><<<(unsigned)M, T / KR, 0, st>>>(kind, box, n, off, S, pinfo, part, runs,
-                                                         rhead, jv[cur], U_idx, U_cum, U_suf,
-                                                         crbase, cr_slot, cr_c, cr_pre, ptot, match,
-                                                         pm, sink, status, n_dyn);
+    // elements per thread of the main pass (more elements per thread share
+    // the partition-level steps among fewer threads)
+    auto resolve = [&](auto kr) {
+        constexpr int KR = decltype(kr)::value;
+        k_resolve<BOXES, V, SINK, KR><<<(unsigned)M, T / KR, 0, st>>>(
+            kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx, U_cum, U_suf, crbase,
+            cr_slot, cr_c, cr_pre, ptot, match, pm, sink, status, n_dyn);
+    };
+    if constexpr (kTunable<BOXES, V, SINK>) {
+        if (var.kr == 8)
+            resolve(std::integral_constant<int, 8>{});
+        else
+            resolve(std::integral_constant<int, 4>{});
+    } else {
+        resolve(std::integral_constant<int, K>{});
+    }
     if (prof) (void)hipEventRecord(g_prof_after, st);
     if (BOXES) {
         void *upre = w + L.upre;
@@ -1560,9 +1585,22 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
             if (L.levels > 1) k_usparse<V><<<1, 1024, 0, st>>>(sp, L.nb, L.levels);
         }
         const int64_t gx = min((int64_t)(n + W - 1) / W, (int64_t)256 * 32);
-        k_cross<V, SINK><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_cum, jv[cur], U_suf,
-                                                      cr_slot, cr_c, cr_pre, upre, usuf, sp, spb, M,
-                                                      L.nb, match, sink);
+        auto cross = [&](auto u) {
+            constexpr int U = decltype(u)::value;
+            k_cross<V, SINK, U><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_cum, jv[cur], U_suf,
+                                                            cr_slot, cr_c, cr_pre, upre, usuf, sp, spb,
+                                                            M, L.nb, match, sink);
+        };
+        if constexpr (kTunable<BOXES, V, SINK>) {
+            if (var.cu == 2)
+                cross(std::integral_constant<int, 2>{});
+            else if (var.cu == 8)
+                cross(std::integral_constant<int, 8>{});
+            else
+                cross(std::integral_constant<int, 4>{});
+        } else {
+            cross(std::integral_constant<int, sizeof(V) <= 16 ? 4 : 2>{});
+        }
     }
     return hipGetLastError();
 }
@@ -1582,16 +1620,16 @@ static uint32_t *prep_status(char *w, const FwdLayout &L, const int64_t *off, in
 
 hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t n,
                    const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
-                   void *ws, uint32_t *status, hipStream_t st) {
+                   void *ws, uint32_t *status, hipStream_t st, Variant var) {
     const FwdLayout L = fwd_layout(n, off ? S : 1, sizeof(Box), false);
     char *w = (char *)ws;
     status = prep_status(w, L, off, S, n, status, st);
     if (n == 0) return hipGetLastError();
     if (boxes)
         return run_pipeline<true, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w,
-                                                L, status, st);
+                                                L, status, st, nullptr, var);
     return run_pipeline<false, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w, L,
-                                             status, st);
+                                             status, st, nullptr, var);
 }
 
 // ------------------------------------------------- no-allocation variant
@@ -1641,7 +1679,8 @@ hipError_t fwd_run_noalloc(const uint32_t *kind, const float4 *box, int64_t n, i
     void *ws = nullptr;
     const hipError_t e = scratch_for(st, &ws);
     if (e != hipSuccess) return e;
-    return fwd_run(true, kind, box, n, nullptr, 1, match, nullptr, out, ws, status, st);
+    return fwd_run(true, kind, box, n, nullptr, 1, match, nullptr, out, ws, status, st,
+                   default_variant(true));
 }
 
 hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,

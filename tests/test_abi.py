@@ -128,3 +128,35 @@ def test_stream_argument_errors(lib):
     lib.tb_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
     need = lib.tb_workspace_bytes(5, 10, 1)
     assert f(A, A, 10, A, A, A, need - 1, A, None) == TB_ERR_WORKSPACE
+
+
+def test_variant_table_host_only(tmp_path):
+    """The variant table works without a device: defaults, pins, invalid
+    variants, save/load round trip, clear."""
+    import paper_2205_11659_amd as tb
+    tb.tune_clear()
+    assert tb.variant_get(tb.OP_BBOX, 1000) == (4, 4, 4)
+    assert tb.variant_get(tb.OP_MATCH, 1 << 20) == (8, 8, 4)
+    tb.variant_set(tb.OP_BBOX, 1 << 20, (8, 4, 2))
+    assert tb.variant_get(tb.OP_BBOX, (1 << 19) + 1) == (8, 4, 2)  # same size class
+    assert tb.variant_get(tb.OP_BBOX, (1 << 20) + 1) == (4, 4, 4)
+    for bad in ((3, 4, 4), (4, 4, 5), (16, 4, 4)):
+        with pytest.raises(tb.TreeBBoxError):
+            tb.variant_set(tb.OP_BBOX, 100, bad)
+    with pytest.raises(tb.TreeBBoxError):
+        tb.variant_set(tb.OP_MATCH, 100, (4, 4, 2))  # matching has no cross pass to vary
+    with pytest.raises(tb.TreeBBoxError):
+        tb.variant_get(tb.OP_COMPOSE, 100)
+    path = tmp_path / "tune.txt"
+    tb.tune_save(str(path))
+    tb.tune_clear()
+    assert tb.variant_get(tb.OP_BBOX, 1 << 20) == (4, 4, 4)
+    tb.tune_load(str(path))
+    assert tb.variant_get(tb.OP_BBOX, 1 << 20) == (8, 4, 2)
+    (tmp_path / "bad.txt").write_text("not a table\n")
+    with pytest.raises(tb.TreeBBoxError):
+        tb.tune_load(str(tmp_path / "bad.txt"))
+    tb.variant_set(tb.OP_BBOX, 1 << 20, None)
+    assert tb.variant_get(tb.OP_BBOX, 1 << 20) == (4, 4, 4)
+    tb.tune_clear()
+    assert len(tb.candidates(tb.OP_BBOX)) == 12 and len(tb.candidates(tb.OP_MATCH)) == 4
