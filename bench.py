@@ -142,7 +142,7 @@ def small_section(reps=100):
     out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     match = torch.empty(n, dtype=torch.int32, device="cuda")
     st = torch.empty(1, dtype=torch.int32, device="cuda")
-    tuned, _ = tb.tune_bbox(kind, box, reps=5)  # untimed: picks the launch variant for this size
+    tuned = tb.tune_bbox(kind, box, reps=5)[0] if TUNE else None  # untimed: picks the launch variant
     tb.tb_bbox(kind, box, match=match, out=out, status=st)
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
@@ -164,7 +164,7 @@ def small_section(reps=100):
     us = a.elapsed_time(b) * 1e3 / reps
     return {"workload": c["name"], "elements": n, "us_per_call": round(us, 2),
             "gelem_s": round(n / us / 1e3, 3), "timing": f"HIP graph of one call, {reps} replays",
-            "autotune": _tune_record(tuned)}
+            "autotune": _tune_record(tuned) if tuned else None}
 
 
 def copy_ceiling(reps=10):
@@ -190,6 +190,9 @@ def copy_ceiling(reps=10):
             "bytes_read_per_copy": nbytes // 2, "frac_of_peak": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+TUNE = True  # sections run the autotuner before timing (off for counter runs)
+
+
 def _tune_record(t):
     """The autotuner's choice for a section: variant (elements per thread of
     the main and the reduce pass, close records per thread of the cross
@@ -200,17 +203,31 @@ def _tune_record(t):
 
 
 def gpu_clocks():
-    """Current GPU clocks as rocm-smi reports them (recorded with the run)."""
-    import subprocess
+    """Current engine (sclk) and memory (mclk) clock levels of the AMD GPUs,
+    read from the driver's sysfs tables (the level marked '*' is current);
+    no subprocess, so it also works under a profiler."""
+    import glob
+    out = {}
     try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
-                           timeout=30)
-        d = json.loads(r.stdout)
-        card = d.get("card0") or next(iter(d.values()))
-        return {k: v for k, v in card.items() if "clock" in k.lower() or "sclk" in k.lower()
-                or "mclk" in k.lower() or "fclk" in k.lower()}
-    except Exception as e:  # a missing tool or unexpected output is reported, not fatal
+        for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+            try:
+                if open(os.path.join(dev, "vendor")).read().strip() != "0x1002":
+                    continue
+            except OSError:
+                continue
+            card = {}
+            for clk in ("pp_dpm_sclk", "pp_dpm_mclk", "pp_dpm_fclk"):
+                try:
+                    lines = open(os.path.join(dev, clk)).read().splitlines()
+                except OSError:
+                    continue
+                cur = [ln.split(":", 1)[1].replace("*", "").strip() for ln in lines if "*" in ln]
+                card[clk[7:]] = cur[0] if cur else None
+            if card:
+                out[os.path.basename(os.path.dirname(dev))] = card
+    except Exception as e:  # unexpected sysfs content is reported, not fatal
         return {"error": str(e)[:200]}
+    return out or {"error": "no AMD GPU clock tables in sysfs"}
 
 
 def c1_section(steps, warmup):
@@ -246,7 +263,7 @@ def batched_section(steps, warmup, cpu=False):
     kind, box = torch.from_numpy(c["kind"].view(np.int32)).cuda(), torch.from_numpy(c["box"]).cuda()
     off = torch.from_numpy(c["offsets"]).cuda()
     out = {}
-    tuned, _ = tb.tune_bbox_batched(kind, box, off, reps=3)
+    tuned = tb.tune_bbox_batched(kind, box, off, reps=3)[0] if TUNE else None
     ms_b = time_steps(lambda: tb.tb_bbox_batched(kind, box, off), steps, warmup)
     bout, bm, bst = tb.tb_bbox_batched(kind, box, off)
     g = tb.PerSceneGraph(kind, box, c["offsets"])
@@ -259,7 +276,7 @@ def batched_section(steps, warmup, cpu=False):
                 "batched_ms": round(ms_b, 4), "batched_gelem_s": round(n / ms_b / 1e6, 3),
                 "per_scene_graph_ms": round(ms_g, 4), "per_scene_graph_gelem_s": round(n / ms_g / 1e6, 3),
                 "speedup": round(ms_g / ms_b, 3), "byte_identical": same,
-                "autotune": _tune_record(tuned)})
+                "autotune": _tune_record(tuned) if tuned else None})
     if cpu:
         out["cpu_baseline_threads"] = oracle_scenes_threads(c["kind"], c["box"], c["offsets"])
     return out
@@ -311,7 +328,7 @@ def match_section(steps, warmup, kind_np=None):
     m = torch.empty(n, dtype=torch.int32, device="cuda")
     pm = torch.empty(n, dtype=torch.int32, device="cuda")
     st = torch.empty(1, dtype=torch.int32, device="cuda")
-    tuned, _ = tb.tune_match(kind, reps=3)
+    tuned = tb.tune_match(kind, reps=3)[0] if TUNE else None
     ms = time_steps(lambda: tb.tb_match(kind, pm=False, match=m, status=st), steps, warmup)
     ms_pm = time_steps(lambda: tb.tb_match(kind, pm=pm, match=m, status=st), steps, warmup)
     torch.cuda.synchronize()
@@ -319,8 +336,29 @@ def match_section(steps, warmup, kind_np=None):
     return {"workload": "scene-128M-chain32M", "elements": n, "ms_per_step": round(ms, 4),
             "gelem_s": round(n / ms / 1e6, 3),
             "hbm_frac_alg": round(8 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "with_pm_ms": round(ms_pm, 4), "autotune": _tune_record(tuned),
+            "with_pm_ms": round(ms_pm, 4), "autotune": _tune_record(tuned) if tuned else None,
             "context": "the paper reports 13.5 Gelem/s for matching alone on a Radeon 5700 XT"}
+
+
+def brackets_section(steps, warmup):
+    """tb_match_brackets on 2^27 typed bracket tokens (8 types, depth cap 64,
+    about half the tokens brackets): 4 B token in, 4 B match out."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    n = 1 << 27
+    tok_np = gen.brackets(n, 64, 8, gen.SEED_BASE + 32)
+    tok = torch.from_numpy(tok_np.view(np.int32)).cuda()
+    del tok_np
+    m = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    ms = time_steps(lambda: tb.tb_match_brackets(tok, pm=False, match=m, status=st), steps, warmup)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return {"workload": "brackets-128M-8types-cap64", "elements": n, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(8 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def compose_section(steps, warmup, kind_np=None):
@@ -394,9 +432,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="time the default launch variant")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
     ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small",
-                                       "c1", "copy"],
+                                       "c1", "copy", "brackets"],
                     help="run one secondary section alone and print its JSON (for profiling)")
     args = ap.parse_args()
+    global TUNE
+    TUNE = not args.no_tune
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the path has no multi-GPU mode", file=sys.stderr)
@@ -404,6 +444,7 @@ def main():
     if args.only:
         fn = {"stream": stream_section, "match": match_section, "compose": compose_section,
               "batched": batched_section, "fwd_bwd": fwd_bwd_section, "c1": c1_section,
+              "brackets": brackets_section,
               "small": lambda st, w: small_section(),
               "copy": lambda st, w: copy_ceiling(max(st, 1))}[args.only]
         print(json.dumps({args.only: fn(args.steps, args.warmup)}), flush=True)
@@ -491,6 +532,8 @@ def main():
         res["match_only"] = match_section(max(3, args.steps // 2), 2, host[0] if host else None)
         torch.cuda.empty_cache()
         res["compose"] = compose_section(max(3, args.steps // 2), 2, host[0] if host else None)
+        torch.cuda.empty_cache()
+        res["brackets"] = brackets_section(max(3, args.steps // 2), 2)
         res["stream"] = stream_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2, cpu=not args.no_cpu)

@@ -45,6 +45,8 @@ def lib():
         L.tbg_raw.argtypes = [P, I64, U64]
         L.tbg_interleave.argtypes = [P, P, I64, I64, ctypes.c_uint32, U64, P, P]
         L.tbg_interleave.restype = ctypes.c_int
+        L.tbg_brackets.argtypes = [P, I64, I64, ctypes.c_uint32, ctypes.c_double, U64]
+        L.tbg_brackets.restype = ctypes.c_int
         L.tbg_splitmix64.argtypes = [U64]
         L.tbg_splitmix64.restype = U64
         for f in (L.tbg_walk, L.tbg_walk_with_chains, L.tbg_chain_around_walk):
@@ -110,6 +112,15 @@ def interleave(kind, box, n, seed, other=OTHER):
     assert rc == 0, rc
     pos = np.flatnonzero(tag != other) if other > 4 else None
     return tag, sbox, pos
+
+
+def brackets(n, cap, ntypes, seed, p_bad=0.0):
+    """Typed bracket tokens (0 none, 2t+1 open type t, 2t+2 close type t)
+    from a depth-capped random walk; p_bad mistypes that fraction of closes."""
+    tok = np.zeros(n, dtype=np.uint32)
+    rc = lib().tbg_brackets(tok.ctypes.data, n, cap, ntypes, p_bad, seed)
+    assert rc == 0, rc
+    return tok
 
 
 def normal(n, seed):

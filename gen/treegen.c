@@ -488,6 +488,46 @@ void tbg_raw(uint64_t *out, int64_t n, uint64_t seed) {
     for (int64_t i = 0; i < n; ++i) out[i] = rng_next(&r);
 }
 
+/* Typed bracket tokens for the parsing workload: the walk rule of tbg_walk
+ * (depth cap `cap`), each open of a type drawn uniformly from [0, ntypes)
+ * and written 2t+1, its close written 2t+2, every other step token 0.  With
+ * probability p_bad a close is written with a different type (ntypes >= 2),
+ * so the input is well nested but mistyped there.  Returns 0 on success. */
+int tbg_brackets(uint32_t *tok, int64_t n, int64_t cap, uint32_t ntypes, double p_bad, uint64_t seed) {
+    if (ntypes < 1) return -1;
+    rng_t r;
+    rng_seed(&r, seed);
+    uint32_t *stk = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(cap + 2));
+    if (!stk) return -1;
+    int64_t d = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t left = n - i;
+        int what = 0; /* 0 none, 1 open, 2 close */
+        if (d == left) {
+            what = 2;
+        } else {
+            const double u = rng_u01(&r);
+            if (u < 0.25 && d < cap && d <= left - 2)
+                what = 1;
+            else if (u < 0.5 && d > 0)
+                what = 2;
+        }
+        if (what == 1) {
+            const uint32_t t = (uint32_t)rng_int(&r, 0, (int64_t)ntypes - 1);
+            stk[d++] = t;
+            tok[i] = 2u * t + 1u;
+        } else if (what == 2) {
+            uint32_t t = stk[--d];
+            if (ntypes >= 2 && rng_u01(&r) < p_bad) t = (t + 1 + (uint32_t)rng_int(&r, 0, ntypes - 2)) % ntypes;
+            tok[i] = 2u * t + 2u;
+        } else {
+            tok[i] = 0u;
+        }
+    }
+    free(stk);
+    return d == 0 ? 0 : -2;
+}
+
 /* A draw-object stream around a tree: the m tree elements (kind, box) keep
  * their order and land on m of the n stream positions, each m-subset of
  * positions equally likely (selection sampling, Knuth TAOCP vol. 2,

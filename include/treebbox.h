@@ -120,6 +120,24 @@ tb_status tb_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm,
                    size_t ws_bytes, uint32_t *dev_status, void *stream);
 
 /*
+ * Matching over typed brackets, the primitive parsers need (section "The
+ * parentheses matching problem" with several kinds of parentheses; the
+ * paper names parsing among the method's applications).  Token 0 is no
+ * bracket, 2t+1 opens a bracket of type t, 2t+2 closes one (so tokens 0..4
+ * are the five element kinds, clip and blend being types 0 and 1).  Every
+ * uint32 is a valid token.  Outputs as for tb_match; a close whose type
+ * differs from its open's still matches it and sets
+ * TB_DATA_KIND_MISMATCH; an unmatched close or open sets
+ * TB_DATA_UNBALANCED.  Workspace: tb_workspace_bytes(TB_OP_MATCH, n, 1).
+ *   tok    [n]  uint32 tokens                                       (in)
+ *   match  [n]  int32 partner index, -1 for token 0                 (out)
+ *   pm     [n]  int32 top of the stack before element i, -1 = root (out, nullable)
+ *   dev_status [1] uint32                                           (out)
+ */
+tb_status tb_match_brackets(const uint32_t *tok, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                            size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
  * Matching plus node boxes: clip intersections down the tree and blend
  * unions up the tree (Introduction; sections "Parallel bounding boxes" and
  * "GPU implementation of clipping and blending").

@@ -40,8 +40,9 @@ def lib():
         L.tbo_sources.argtypes = [P, P, I64, P]
         L.tbo_compose.argtypes = [P, P, I64, P]
         L.tbo_bbox_stream.argtypes = [P, P, I64, P, P]
+        L.tbo_match_brackets.argtypes = [P, I64, P, P]
         for f in (L.tbo_bbox, L.tbo_match, L.tbo_bbox_f64, L.tbo_backward, L.tbo_sources,
-                  L.tbo_compose, L.tbo_bbox_stream):
+                  L.tbo_compose, L.tbo_bbox_stream, L.tbo_match_brackets):
             f.restype = U32
         _lib = L
     return _lib
@@ -71,6 +72,17 @@ def match(kind):
     m = np.empty(n, np.int32)
     pm = np.empty(n, np.int32)
     st = lib().tbo_match(kind.ctypes.data, n, m.ctypes.data, pm.ctypes.data)
+    return m, pm, int(st)
+
+
+def match_brackets(tok):
+    """Typed bracket matching: token 0 none, 2t+1 open type t, 2t+2 close
+    type t.  Returns (match int32[n], pm int32[n], status)."""
+    tok = _c(tok, np.uint32)
+    n = tok.shape[0]
+    m = np.empty(n, np.int32)
+    pm = np.empty(n, np.int32)
+    st = lib().tbo_match_brackets(tok.ctypes.data, n, m.ctypes.data, pm.ctypes.data)
     return m, pm, int(st)
 
 

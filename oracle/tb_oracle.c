@@ -169,6 +169,49 @@ uint32_t tbo_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm)
     return tbo_bbox(kind, NULL, n, match, pm, NULL);
 }
 
+/*
+ * Matching over typed brackets (section "The parentheses matching problem",
+ * Fig. 1, with several kinds of parentheses as parsing needs them).
+ * Token 0 is not a bracket; an odd token 2t+1 opens a bracket of type t, an
+ * even token 2t+2 closes one.  Tokens 0..4 are exactly the five element
+ * kinds (types 0 and 1 being clip and blend), so on them this equals
+ * tbo_match.  The walk is Fig. 1's stack; a close whose type differs from
+ * its open's sets KIND_MISMATCH and still matches that open; a close with
+ * nothing open, or an open never closed, sets UNBALANCED.  Every uint32 is
+ * a valid token (no BAD_KIND).
+ */
+uint32_t tbo_match_brackets(const uint32_t *tok, int64_t n, int32_t *match, int32_t *pm) {
+    uint32_t status = 0;
+    int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!S) return 0xFFFFFFFFu;
+    int64_t sp = 0;
+    S[sp++] = -1; /* the root */
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t top = S[sp - 1];
+        if (pm) pm[i] = (int32_t)top;
+        if (match) match[i] = -1;
+        const uint32_t k = tok[i];
+        if (k == 0) continue;
+        if (k & 1u) {
+            S[sp++] = i;
+            continue;
+        }
+        if (top == -1) {
+            status |= ST_UNBALANCED;
+            continue;
+        }
+        if (tok[top] + 1u != k) status |= ST_KIND_MISMATCH;
+        --sp;
+        if (match) {
+            match[i] = (int32_t)top;
+            match[top] = (int32_t)i;
+        }
+    }
+    if (sp != 1) status |= ST_UNBALANCED;
+    free(S);
+    return status;
+}
+
 /* The same forward walk in fp64 (for finite-difference checks). */
 uint32_t tbo_bbox_f64(const uint32_t *kind, const double *box, int64_t n, double *out) {
     uint32_t status = 0;

@@ -45,6 +45,8 @@ def lib():
         L.tb_workspace_bytes.restype = SZ
         L.tb_match.argtypes = [P, I64, P, P, P, SZ, P, P]
         L.tb_bbox.argtypes = [P, P, I64, P, P, P, SZ, P, P]
+        L.tb_match_brackets.argtypes = [P, I64, P, P, P, SZ, P, P]
+        L.tb_match_brackets.restype = ctypes.c_int
         L.tb_bbox_backward.argtypes = [P, P, P, I64, P, P, SZ, P, P]
         L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
         L.tb_compose.argtypes = [P, P, I64, P, P, SZ, P, P]
@@ -159,6 +161,24 @@ def tb_match(kind, pm=True, match=None, status=None):
     ws, wsb = workspace(OP_MATCH, n, 1, dev)
     _check(lib().tb_match(_ptr(kind), n, _ptr(match), _ptr(pmo), ctypes.c_void_p(ws), wsb,
                           _ptr(status), _stream()))
+    return match, pmo, status
+
+
+def tb_match_brackets(tok, pm=True, match=None, status=None):
+    """Typed bracket matching (token 0 none, 2t+1 open type t, 2t+2 close
+    type t): returns (match int32[n], pm int32[n] or None, status int32[1])."""
+    tok = _as_kind(tok)
+    n = tok.numel()
+    dev = tok.device
+    match = torch.empty(n, dtype=torch.int32, device=dev) if match is None else match
+    if isinstance(pm, torch.Tensor):
+        pmo = pm
+    else:
+        pmo = torch.empty(n, dtype=torch.int32, device=dev) if pm else None
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    ws, wsb = workspace(OP_MATCH, n, 1, dev)
+    _check(lib().tb_match_brackets(_ptr(tok), n, _ptr(match), _ptr(pmo), ctypes.c_void_p(ws), wsb,
+                                   _ptr(status), _stream()))
     return match, pmo, status
 
 

@@ -65,6 +65,18 @@ tb_status tb_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm,
                                 dev_status, (hipStream_t)stream, tb::variant_for(TB_OP_MATCH, n, false)));
 }
 
+tb_status tb_match_brackets(const uint32_t *tok, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                            size_t ws_bytes, uint32_t *dev_status, void *stream) {
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!dev_status || (n > 0 && !match)) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (match && !aligned(match, 4)) || (pm && !aligned(pm, 4)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(tok, n, ws, ws_bytes, TB_OP_MATCH, 1);
+    if (c != TB_OK) return c;
+    return launched(tb::brackets_run(tok, n, match, pm, ws, dev_status, (hipStream_t)stream,
+                                     tb::variant_for(TB_OP_MATCH, n, false)));
+}
+
 tb_status tb_bbox(const uint32_t *kind, const tb_box *box_in, int64_t n, int32_t *match,
                   tb_box *box_out, void *ws, size_t ws_bytes, uint32_t *dev_status,
                   void *stream) {

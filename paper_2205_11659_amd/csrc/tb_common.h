@@ -359,6 +359,12 @@ __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *tota
     return op(pre, ex);
 }
 
+// Typed bracket tokens: 0 is no bracket, 2t+1 opens type t, 2t+2 closes it;
+// the structure alone, as kinds
+__device__ __forceinline__ uint32_t bracket_kind(uint32_t tok) {
+    return tok == 0u ? (uint32_t)LEAF : (tok & 1u) ? (uint32_t)BCLIP : (uint32_t)ECLIP;
+}
+
 // both open kinds as BEGIN_CLIP and both closes as END_CLIP (payloads that
 // every open carries)
 __device__ __forceinline__ uint32_t as_clip(uint32_t k) {

@@ -47,6 +47,11 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
                    const int64_t *off, int64_t S, int32_t *match, int32_t *pm, float4 *out,
                    void *ws, uint32_t *status, hipStream_t st, Variant var);
 
+// Matching over typed bracket tokens (0 none, 2t+1 open type t, 2t+2 close
+// type t): a close whose type differs from its open's sets KIND_MISMATCH.
+hipError_t brackets_run(const uint32_t *tok, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                        uint32_t *status, hipStream_t st, Variant var);
+
 // Transform composition down the tree: xf and out hold 24-byte rows
 // [a b c d e f] (uint32, 8-byte aligned).
 hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,

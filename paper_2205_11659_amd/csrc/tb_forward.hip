@@ -78,7 +78,7 @@ __global__ void k_offsets_flag(const uint32_t *flagw, int64_t S, uint32_t *statu
 // thread (coalesced loads and stores).  Prefix and suffix bicyclic products
 // over threads come from DPP wave scans plus the four wave totals, so the
 // whole kernel needs two barriers.
-template <bool BOXES, class V, int KK>
+template <bool BOXES, class V, int KK, bool BRK = false>
 __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ kind,
                                               const float4 *__restrict__ box, int64_t n,
                                               const int64_t *__restrict__ off, int64_t S,
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     load_kinds<KK>(kind, n, g0, ks);
 #pragma unroll
     for (int j = 0; j < KK; ++j)
-        ks[j] = ks[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(ks[j]) : ks[j];
+        ks[j] = BRK ? bracket_kind(ks[j]) : ks[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(ks[j]) : ks[j];
     const uint32_t rm = reset_mask<KK>(off, S, n, g0);
     const Walk wk = walk_kinds<KK>(ks, rm);
     const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
@@ -544,7 +544,7 @@ struct ResolveSmem {
     V wtot[NW];  // union of each wave's leaves
 };
 
-template <bool BOXES, class V, class SINK, int KK>
+template <bool BOXES, class V, class SINK, int KK, bool BRK = false>
 __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) void k_resolve(
     const uint32_t *__restrict__ kind, const float4 *__restrict__ box, int64_t n,
     const int64_t *__restrict__ off, int64_t S, const int4 *__restrict__ pinfo,
@@ -591,7 +591,9 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
-    for (int j = 0; j < KK; ++j) ks[j] = kr[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(kr[j]) : kr[j];
+    for (int j = 0; j < KK; ++j)
+        ks[j] = BRK ? bracket_kind(kr[j]) : kr[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(kr[j]) : kr[j];
+    static_assert(!BRK || !BOXES, "typed brackets are matched without payloads");
     const uint32_t rm = reset_mask<KK>(off, S, n, g0);
     __syncthreads();
 
@@ -651,6 +653,12 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (x > aP) continue;
         sm.e.w.inc_idx[x] = g_idx[q];
         if (BOXES) sm.cx[x] = g_ctx[q];
+        // a clip level popped here: its close record carries the open's full
+        // context, which is the pair's box (blend records get their prefix
+        // union in the union phase)
+        if (BOXES && x >= 1 && g_idx[q] != -1 && !((uint32_t)g_idx[q] & BLEND_BIT) &&
+            (uint32_t)(rbase + aP - x) < un)
+            Pay<V>::st(cr_pre, rbase + aP - x, g_ctx[q]);
     }
     int wmin0;
     int premin = wave_excl_scan(cm, MinOp{}, INT32_MAX, &wmin0);  // lowest level of earlier lanes
@@ -737,6 +745,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     uint32_t keep = 0;    // rows this thread writes at the end
     uint32_t mkeep = 0;   // match rows this thread writes at the end
     uint32_t lbm = 0;     // closes of blends opened in this thread
+    uint32_t rchk = 0;    // typed brackets: closes whose open's token is checked after the walk
     uint32_t defmask = 0; // closes of blends opened before this thread
     uint64_t errs = 0;    // status bits, 4 per element; element g0 - 1 at bit 4KK
     bool rseen = false;
@@ -777,7 +786,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
                 soff = (int)off[sid];
             }
         }
-        if (real && kr[j] > 4u) errs |= (uint64_t)ST_BAD_KIND << (4 * j);
+        if (!BRK && real && kr[j] > 4u) errs |= (uint64_t)ST_BAD_KIND << (4 * j);
         const int tp = mask ? msb32(mask) : -1;
         if (tp < 0 && !rseen && cur_L != dep) {
             cur_L = dep;
@@ -856,8 +865,20 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
             // context inside its open.  Blend rows are filled in later.
             res[j] = canon((isleaf && Pay<V>::kLeafOwn) || k == BCLIP ? ix : ctx);
         }
-        const bool mism = (lclose && ((k == ECLIP) != (((clipm >> tps) & 1u) != 0))) ||
-                          (rok && ((k == ECLIP) != (cur_kind == (int)BCLIP)));
+        bool mism;
+        if (BRK) {
+            // a close must carry its open's token plus one; an open in an
+            // earlier thread is checked after the walk (a global read)
+            uint32_t otok = 0;
+#pragma unroll
+            for (int q = 0; q < j; ++q)
+                if (q == tps) otok = kr[q];
+            mism = lclose && kr[j] != otok + 1u;
+            rchk |= (rok && real) ? bit : 0u;
+        } else {
+            mism = (lclose && ((k == ECLIP) != (((clipm >> tps) & 1u) != 0))) ||
+                   (rok && ((k == ECLIP) != (cur_kind == (int)BCLIP)));
+        }
         errs |= (real && mism) ? (uint64_t)ST_MISMATCH << (4 * j) : 0u;
         errs |= (real && (rootclose || (rclose && !rok))) ? (uint64_t)ST_UNBAL << (4 * j) : 0u;
         leafm |= isleaf ? bit : 0u;
@@ -883,6 +904,19 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (rec) cr_c[rbase + ci] = (int32_t)(i | (k == EBLEND ? 0x80000000u : 0u));
         mask = isopen ? (mask | bit) : (mask & ~pbit);
         dep += isopen ? 1 : (lclose || rclose) ? -1 : 0;
+    }
+    if (BRK && __ballot(rchk != 0)) {
+        // closes of opens held by earlier threads: compare with the open's
+        // token, every read in flight before the first compare
+        uint32_t otok[KK];
+#pragma unroll
+        for (int j = 0; j < KK; ++j) {
+            const uint32_t oi = (uint32_t)mv[j] + (uint32_t)soff;
+            otok[j] = ((rchk >> j) & 1u) && oi < un ? kind[oi] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < KK; ++j)
+            if (((rchk >> j) & 1u) && kr[j] != otok[j] + 1u) errs |= (uint64_t)ST_MISMATCH << (4 * j);
     }
     if (errs) {  // malformed input only: raise each element's bits in its scene's word
 #pragma unroll
@@ -1063,8 +1097,6 @@ template <class V, class SINK, int U>
 __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int64_t n,
                                              const int64_t *__restrict__ off, int64_t S,
                                              const int32_t *__restrict__ U_idx,
-                                             const void *__restrict__ U_cum,
-                                             const void *__restrict__ base_ctx,
                                              const void *__restrict__ U_suf,
                                              const int32_t *__restrict__ cr_slot,
                                              const int32_t *__restrict__ cr_c,
@@ -1077,10 +1109,10 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
     // One thread per close record: a close whose open lies in an earlier
     // partition.  Both rows and both match entries of the pair are written
     // here, so consecutive records write consecutive rows.  A clip pair's box
-    // is the open's full clip context (its partition-local prefix intersected
-    // with the context at that partition's base); a blend pair's is the union
-    // of the open's suffix, the whole partitions between and the close's
-    // prefix.  Records are dense and their count is on the device.  A
+    // is the open's full clip context, which k_resolve put in the record
+    // (read densely here, whatever the kinds of the neighbouring records); a
+    // blend pair's is the union of the open's suffix, the whole partitions
+    // between and the close's prefix (the record's payload).  Records are dense and their count is on the device.  A
     // workgroup takes contiguous chunks of U*W records, U per thread; after
     // the records themselves every load is issued at once (unused lanes read
     // entry 0 and discard it).
@@ -1109,10 +1141,12 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
             ok[q] = sl[q] >= 0 && sl[q] < M * T && cc[q] >= 0 && cc[q] < n && sl[q] / T < cc[q] / T;
             const int64_t s0 = ok[q] ? sl[q] : 0;
             ui[q] = U_idx[s0];
-            // only the loads this kind of pair uses (the others read entry 0)
-            const int64_t sc = bl[q] ? 0 : s0, sb = bl[q] ? s0 : 0;
-            cl[q] = isect(Pay<V>::ld(base_ctx, sc / T), Pay<V>::ld(U_cum, sc));
-            part[q] = unite(Pay<V>::ld(U_suf, sb), Pay<V>::ld(cr_pre, ok[q] && bl[q] ? r : 0));
+            // the record's payload: a clip pair's box (the open's full
+            // context), or a blend close's prefix union; a blend pair also
+            // needs the open's suffix union (other lanes read entry 0)
+            const V pre = Pay<V>::ld(cr_pre, ok[q] ? r : 0);
+            cl[q] = pre;
+            part[q] = unite(Pay<V>::ld(U_suf, bl[q] ? s0 : 0), pre);
             // whole partitions strictly between: [a, b]
             const int64_t a = ok[q] && bl[q] ? sl[q] / T + 1 : 1, b = ok[q] && bl[q] ? cc[q] / T - 1 : 0;
             ne[q] = a <= b;
@@ -1490,14 +1524,16 @@ FwdLayout fwd_layout(int64_t n, int64_t S, size_t vbytes, bool grad) {
 template <bool BOXES, class V, class SINK>
 constexpr bool kTunable = !BOXES || (std::is_same<V, Box>::value && std::is_same<SINK, SinkOut>::value);
 
-template <bool BOXES, class V, class SINK, int KD>
+template <bool BOXES, class V, class SINK, int KD, bool BRK>
 static void launch_reduce(int64_t M, hipStream_t st, const uint32_t *kind, const float4 *box, int64_t n,
                           const int64_t *off, int64_t S, int4 *pinfo, int32_t *U_idx, void *U_cum,
                           const int64_t *n_dyn) {
-    k_reduce<BOXES, V, KD><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+    k_reduce<BOXES, V, KD, BRK><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum,
+                                                               n_dyn);
 }
 
-template <bool BOXES, class V, class SINK>
+// BRK: the kinds are typed bracket tokens (matching alone)
+template <bool BOXES, class V, class SINK, bool BRK = false>
 static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t n,
                                const int64_t *off, int64_t S, int32_t *match, int32_t *pm,
                                SINK sink, char *w, const FwdLayout &L, uint32_t *status,
@@ -1514,9 +1550,9 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     void *U_cum = w + L.U_cum;
     // elements per thread of the reduce
     if (var.kd == 8)
-        launch_reduce<BOXES, V, SINK, 8>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+        launch_reduce<BOXES, V, SINK, 8, BRK>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
     else
-        launch_reduce<BOXES, V, SINK, 4>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+        launch_reduce<BOXES, V, SINK, 4, BRK>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
@@ -1562,7 +1598,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     // the partition-level steps among fewer threads)
     auto resolve = [&](auto kr) {
         constexpr int KR = decltype(kr)::value;
-        k_resolve<BOXES, V, SINK, KR><<<(unsigned)M, T / KR, 0, st>>>(
+        k_resolve<BOXES, V, SINK, KR, BRK><<<(unsigned)M, T / KR, 0, st>>>(
             kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx, U_cum, U_suf, crbase,
             cr_slot, cr_c, cr_pre, ptot, match, pm, sink, status, n_dyn);
     };
@@ -1587,7 +1623,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
         const int64_t gx = min((int64_t)(n + W - 1) / W, (int64_t)256 * 32);
         auto cross = [&](auto u) {
             constexpr int U = decltype(u)::value;
-            k_cross<V, SINK, U><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_cum, jv[cur], U_suf,
+            k_cross<V, SINK, U><<<(unsigned)gx, W, 0, st>>>(crtot, n, off, S, U_idx, U_suf,
                                                             cr_slot, cr_c, cr_pre, upre, usuf, sp, spb,
                                                             M, L.nb, match, sink);
         };
@@ -1672,6 +1708,16 @@ hipError_t scratch_for(hipStream_t st, void **out) {
     return hipSuccess;
 }
 }  // namespace
+
+hipError_t brackets_run(const uint32_t *tok, int64_t n, int32_t *match, int32_t *pm, void *ws,
+                        uint32_t *status, hipStream_t st, Variant var) {
+    const FwdLayout L = fwd_layout(n, 1, sizeof(Box), false);
+    char *w = (char *)ws;
+    status = prep_status(w, L, nullptr, 1, n, status, st);
+    if (n == 0) return hipGetLastError();
+    return run_pipeline<false, Box, SinkOut, true>(tok, nullptr, n, nullptr, 1, match, pm, SinkOut{nullptr},
+                                                   w, L, status, st, nullptr, var);
+}
 
 hipError_t fwd_run_noalloc(const uint32_t *kind, const float4 *box, int64_t n, int32_t *match,
                            float4 *out, uint32_t *status, hipStream_t st) {
