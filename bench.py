@@ -385,6 +385,30 @@ def compose_section(steps, warmup, kind_np=None):
             "hbm_frac_alg": round(52 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def compose_f32_section(steps, warmup):
+    """tb_compose_f32 (fp32 transforms, pointer-jumping order) on a 2^24
+    cap-256 walk: matching, then ceil(log2(depth + 1)) rounds over all
+    elements; algorithmic bytes: kind 4 + transform 24 in, transform 24 out."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    c = gen.config(4)
+    n = len(c["kind"])
+    kind = torch.from_numpy(c["kind"].view(np.int32)).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(gen.SEED_BASE + 40)
+    xf = torch.rand((n, 6), generator=g, device="cuda") * 2 - 1
+    out = torch.empty_like(xf)
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    ms = time_steps(lambda: tb.tb_compose_f32(kind, xf, out=out, status=st), steps, warmup)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return {"workload": "scene-16M-cap256", "elements": n, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(52 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def stream_section(steps, warmup):
     """tb_bbox_stream on a draw-object stream of 2^27 elements holding a
     cap-64 random-walk tree of 2^24 elements (density 1/8).  Algorithmic
@@ -432,7 +456,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="time the default launch variant")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
     ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small",
-                                       "c1", "copy", "brackets"],
+                                       "c1", "copy", "brackets", "compose_f32"],
                     help="run one secondary section alone and print its JSON (for profiling)")
     args = ap.parse_args()
     global TUNE
@@ -444,7 +468,7 @@ def main():
     if args.only:
         fn = {"stream": stream_section, "match": match_section, "compose": compose_section,
               "batched": batched_section, "fwd_bwd": fwd_bwd_section, "c1": c1_section,
-              "brackets": brackets_section,
+              "brackets": brackets_section, "compose_f32": compose_f32_section,
               "small": lambda st, w: small_section(),
               "copy": lambda st, w: copy_ceiling(max(st, 1))}[args.only]
         print(json.dumps({args.only: fn(args.steps, args.warmup)}), flush=True)
@@ -534,6 +558,7 @@ def main():
         res["compose"] = compose_section(max(3, args.steps // 2), 2, host[0] if host else None)
         torch.cuda.empty_cache()
         res["brackets"] = brackets_section(max(3, args.steps // 2), 2)
+        res["compose_f32"] = compose_f32_section(max(3, args.steps // 2), 2)
         res["stream"] = stream_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2, cpu=not args.no_cpu)

@@ -102,6 +102,7 @@ typedef enum {
 #define TB_OP_BBOX_BATCHED 3
 #define TB_OP_COMPOSE 4
 #define TB_OP_BBOX_STREAM 5
+#define TB_OP_COMPOSE_F32 6
 
 /* Workspace bytes needed by `op` for n elements (num_scenes is used by
    TB_OP_BBOX_BATCHED only; pass 1 otherwise).  Returns 0 for invalid sizes. */
@@ -223,6 +224,30 @@ tb_status tb_bbox_batched(const uint32_t *kind, const tb_box *box_in, const int6
  */
 tb_status tb_compose(const uint32_t *kind, const tb_affine *xf_in, int64_t n, tb_affine *xf_out,
                      void *ws, size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
+ * Composition of fp32 transforms down the tree: a monoid whose products
+ * round, so the combine order is part of the result.  The order is that of
+ * pointer jumping over the opens (section "Parallel bounding boxes", Clips):
+ * every open starts with its own transform and a pointer to its enclosing
+ * open; in each round all opens at once replace their value v by (value at
+ * the pointer) . v and their pointer by the pointer's pointer, from the
+ * previous round's values, until no pointer is left.  A leaf takes the value
+ * of the open enclosing it (the identity at the root), a close that of its
+ * open.  p . q applies q first; every product and every sum is one fp32
+ * operation rounded to nearest even, no fused multiply-add:
+ *   a = p.a*q.a + p.b*q.d,  b = p.a*q.b + p.b*q.e,  c = (p.a*q.c + p.b*q.f) + p.c,
+ *   d = p.d*q.a + p.e*q.d,  e = p.d*q.b + p.e*q.e,  f = (p.d*q.c + p.e*q.f) + p.f.
+ * Rounds cost a pass over all elements each; ceil(log2(depth + 1)) of them
+ * do work (later launches return at once).
+ *   kind   [n]  uint32 tb_kind values                                  (in)
+ *   xf_in  [n]  6 floats [a b c d e f] per row, rows of opens used, 8-byte aligned (in)
+ *   xf_out [n]  6 floats, the composed transform per element          (out)
+ *   dev_status [1] uint32: as tb_match                                  (out)
+ * Workspace: tb_workspace_bytes(TB_OP_COMPOSE_F32, n, 1).
+ */
+tb_status tb_compose_f32(const uint32_t *kind, const float *xf_in, int64_t n, float *xf_out, void *ws,
+                         size_t ws_bytes, uint32_t *dev_status, void *stream);
 
 /*
  * Node boxes over a draw-object stream (Introduction: a renderer extracts

@@ -22,7 +22,9 @@ _lib = None
 def build():
     """Compile the oracle library in place (gcc -O2, host only)."""
     tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+    # -ffp-contract=off: every fp32 multiply and add rounds on its own
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-shared", "-fPIC", "-o", tmp,
+                           _SRC, "-lm"])
     os.replace(tmp, LIB_PATH)
 
 
@@ -41,8 +43,11 @@ def lib():
         L.tbo_compose.argtypes = [P, P, I64, P]
         L.tbo_bbox_stream.argtypes = [P, P, I64, P, P]
         L.tbo_match_brackets.argtypes = [P, I64, P, P]
+        L.tbo_compose_f32.argtypes = [P, P, I64, P]
+        L.tbo_reduce_up_f32.argtypes = [P, P, I64, P]
         for f in (L.tbo_bbox, L.tbo_match, L.tbo_bbox_f64, L.tbo_backward, L.tbo_sources,
-                  L.tbo_compose, L.tbo_bbox_stream, L.tbo_match_brackets):
+                  L.tbo_compose, L.tbo_bbox_stream, L.tbo_match_brackets, L.tbo_compose_f32,
+                  L.tbo_reduce_up_f32):
             f.restype = U32
         _lib = L
     return _lib
@@ -122,6 +127,28 @@ def compose(kind, xf):
     n = kind.shape[0]
     out = np.empty((n, 6), np.uint32)
     st = lib().tbo_compose(kind.ctypes.data, xf.ctypes.data, n, out.ctypes.data)
+    return out, int(st)
+
+
+def compose_f32(kind, xf):
+    """fp32 transforms composed down the tree in pointer-jumping order:
+    xf float32[n,6] rows [a b c d e f].  Returns (out float32[n,6], status)."""
+    kind = _c(kind, np.uint32)
+    xf = _c(xf, np.float32).reshape(-1, 6)
+    n = kind.shape[0]
+    out = np.empty((n, 6), np.float32)
+    st = lib().tbo_compose_f32(kind.ctypes.data, xf.ctypes.data, n, out.ctypes.data)
+    return out, int(st)
+
+
+def reduce_up_f32(kind, xf):
+    """fp32 transforms of the leaves multiplied up the tree (segment-tree
+    grouping).  Returns (out float32[n,6], status)."""
+    kind = _c(kind, np.uint32)
+    xf = _c(xf, np.float32).reshape(-1, 6)
+    n = kind.shape[0]
+    out = np.full((n, 6), np.nan, np.float32)
+    st = lib().tbo_reduce_up_f32(kind.ctypes.data, xf.ctypes.data, n, out.ctypes.data)
     return out, int(st)
 
 

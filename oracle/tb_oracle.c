@@ -170,6 +170,150 @@ uint32_t tbo_match(const uint32_t *kind, int64_t n, int32_t *match, int32_t *pm)
 }
 
 /*
+ * fp32 affine transforms composed down the tree, a monoid whose products
+ * round, so the combine order is part of the definition.  The order is that
+ * of pointer jumping (section "Parallel bounding boxes", Clips): every open
+ * holds a value and a pointer to its enclosing open; in each round all of
+ * them at once replace value v by (value at the pointer) . v and the pointer
+ * by the pointer's pointer, reading the previous round's arrays, until no
+ * pointer is left.  After round r an open holds the product over itself and
+ * its 2^r - 1 nearest enclosing opens, outermost first.  Leaves take the
+ * final value of the open enclosing them (the identity at the root) and a
+ * close that of its open.
+ *
+ * Product p.q (q applied first), every operation an fp32 operation rounded
+ * to nearest even, no fused multiply-add:
+ *   a = p.a*q.a + p.b*q.d          b = p.a*q.b + p.b*q.e
+ *   c = (p.a*q.c + p.b*q.f) + p.c
+ *   d = p.d*q.a + p.e*q.d          e = p.d*q.b + p.e*q.e
+ *   f = (p.d*q.c + p.e*q.f) + p.f
+ * (each x*y rounded, then each + rounded, left to right as written).
+ * Status: as tbo_match (kind pairs are not checked).
+ */
+typedef struct { float a, b, c, d, e, f; } aff32;
+static aff32 aff32_id(void) { aff32 r = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f}; return r; }
+static float mul_rn(float x, float y) { volatile float r = x * y; return r; }
+static float add_rn(float x, float y) { volatile float r = x + y; return r; }
+static aff32 aff32_mul(aff32 p, aff32 q) {
+    aff32 r;
+    r.a = add_rn(mul_rn(p.a, q.a), mul_rn(p.b, q.d));
+    r.b = add_rn(mul_rn(p.a, q.b), mul_rn(p.b, q.e));
+    r.c = add_rn(add_rn(mul_rn(p.a, q.c), mul_rn(p.b, q.f)), p.c);
+    r.d = add_rn(mul_rn(p.d, q.a), mul_rn(p.e, q.d));
+    r.e = add_rn(mul_rn(p.d, q.b), mul_rn(p.e, q.e));
+    r.f = add_rn(add_rn(mul_rn(p.d, q.c), mul_rn(p.e, q.f)), p.f);
+    return r;
+}
+
+uint32_t tbo_compose_f32(const uint32_t *kind, const float *xf, int64_t n, float *out) {
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    int32_t *pm = (int32_t *)malloc(sizeof(int32_t) * m);
+    aff32 *val = (aff32 *)malloc(sizeof(aff32) * m), *nval = (aff32 *)malloc(sizeof(aff32) * m);
+    int64_t *ptr = (int64_t *)malloc(sizeof(int64_t) * m), *nptr = (int64_t *)malloc(sizeof(int64_t) * m);
+    if (!pm || !val || !nval || !ptr || !nptr) return 0x80000000u;
+    const uint32_t status = tbo_match(kind, n, NULL, pm);
+    int any = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int open = kind[i] == BEGIN_CLIP || kind[i] == BEGIN_BLEND;
+        const float *x = xf + 6 * i;
+        aff32 own = {x[0], x[1], x[2], x[3], x[4], x[5]};
+        val[i] = open ? own : aff32_id();
+        ptr[i] = open ? pm[i] : -1;
+        any |= ptr[i] >= 0;
+    }
+    while (any) { /* one round: every pointer at once, from the previous arrays */
+        any = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t p = ptr[i];
+            if (p >= 0) {
+                nval[i] = aff32_mul(val[p], val[i]);
+                nptr[i] = ptr[p];
+            } else {
+                nval[i] = val[i];
+                nptr[i] = -1;
+            }
+            any |= nptr[i] >= 0;
+        }
+        aff32 *tv = val; val = nval; nval = tv;
+        int64_t *tp = ptr; ptr = nptr; nptr = tp;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const int open = kind[i] == BEGIN_CLIP || kind[i] == BEGIN_BLEND;
+        const aff32 o = open ? val[i] : pm[i] >= 0 ? val[pm[i]] : aff32_id();
+        float *y = out + 6 * i;
+        y[0] = o.a, y[1] = o.b, y[2] = o.c, y[3] = o.d, y[4] = o.e, y[5] = o.f;
+    }
+    free(pm), free(val), free(nval), free(ptr), free(nptr);
+    return status;
+}
+
+/*
+ * fp32 transforms combined UP the tree: an open (and its close) gets the
+ * ordered product of the transforms of the leaves strictly between them,
+ * in sequence order, the leftmost leaf the leftmost factor (p.q as in
+ * tbo_compose_f32); an open with no leaf inside gets the identity; a leaf
+ * gets its own transform.  Products round, so the grouping is fixed: that
+ * of a segment tree over the positions.  With N the smallest power of two
+ * >= n, node N+i holds element i's transform if it is a leaf and nothing
+ * otherwise, node v combines nodes 2v and 2v+1 (a missing side leaves the
+ * other unchanged), and a range [lo, hi] is answered bottom-up:
+ *   l = lo+N, r = hi+N+1, L = R = nothing;
+ *   while l < r: if l odd, L = L.node[l++]; if r odd, R = node[--r].R;
+ *                l /= 2, r /= 2;
+ *   result L.R.
+ * Status: as tbo_match.
+ */
+typedef struct { aff32 v; int some; } aff32o; /* some = 0: no leaf */
+static aff32o comb32(aff32o a, aff32o b) {
+    if (!a.some) return b;
+    if (!b.some) return a;
+    aff32o r = {aff32_mul(a.v, b.v), 1};
+    return r;
+}
+
+uint32_t tbo_reduce_up_f32(const uint32_t *kind, const float *xf, int64_t n, float *out) {
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    int32_t *match = (int32_t *)malloc(sizeof(int32_t) * m);
+    int64_t N = 1;
+    while (N < n) N <<= 1;
+    aff32o *node = (aff32o *)calloc((size_t)(2 * N), sizeof(aff32o));
+    if (!match || !node) return 0x80000000u;
+    const uint32_t status = tbo_match(kind, n, match, NULL);
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind[i] != LEAF) continue;
+        const float *x = xf + 6 * i;
+        aff32o leaf = {{x[0], x[1], x[2], x[3], x[4], x[5]}, 1};
+        node[N + i] = leaf;
+    }
+    for (int64_t v = N - 1; v >= 1; --v) node[v] = comb32(node[2 * v], node[2 * v + 1]);
+    for (int64_t i = 0; i < n; ++i) {
+        aff32 o = aff32_id();
+        if (kind[i] == LEAF) {
+            o = node[N + i].v;
+        } else if ((kind[i] == BEGIN_CLIP || kind[i] == BEGIN_BLEND) && match[i] > i) {
+            aff32o L = {aff32_id(), 0}, R = {aff32_id(), 0};
+            int64_t l = i + 1 + N, r = (int64_t)match[i] - 1 + N + 1;
+            while (l < r) {
+                if (l & 1) L = comb32(L, node[l++]);
+                if (r & 1) R = comb32(node[--r], R);
+                l >>= 1;
+                r >>= 1;
+            }
+            const aff32o q = comb32(L, R);
+            if (q.some) o = q.v;
+        } else if ((kind[i] == END_CLIP || kind[i] == END_BLEND) && match[i] >= 0 && match[i] < i) {
+            continue; /* written with its open below */
+        }
+        float *y = out + 6 * i;
+        y[0] = o.a, y[1] = o.b, y[2] = o.c, y[3] = o.d, y[4] = o.e, y[5] = o.f;
+        if ((kind[i] == BEGIN_CLIP || kind[i] == BEGIN_BLEND) && match[i] > i)
+            memcpy(out + 6 * (int64_t)match[i], y, 6 * sizeof(float));
+    }
+    free(match), free(node);
+    return status;
+}
+
+/*
  * Matching over typed brackets (section "The parentheses matching problem",
  * Fig. 1, with several kinds of parentheses as parsing needs them).
  * Token 0 is not a bracket; an odd token 2t+1 opens a bracket of type t, an

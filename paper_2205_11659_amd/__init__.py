@@ -24,7 +24,7 @@ DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS, DATA_GRAD_
 _DATA_NAMES = {DATA_BAD_KIND: "BAD_KIND", DATA_UNBALANCED: "UNBALANCED",
                DATA_KIND_MISMATCH: "KIND_MISMATCH", DATA_BAD_OFFSETS: "BAD_OFFSETS",
                DATA_GRAD_RANGE: "GRAD_RANGE"}
-OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE, OP_BBOX_STREAM = range(6)
+OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE, OP_BBOX_STREAM, OP_COMPOSE_F32 = range(7)
 
 _lib = None
 
@@ -46,6 +46,8 @@ def lib():
         L.tb_match.argtypes = [P, I64, P, P, P, SZ, P, P]
         L.tb_bbox.argtypes = [P, P, I64, P, P, P, SZ, P, P]
         L.tb_match_brackets.argtypes = [P, I64, P, P, P, SZ, P, P]
+        L.tb_compose_f32.argtypes = [P, P, I64, P, P, SZ, P, P]
+        L.tb_compose_f32.restype = ctypes.c_int
         L.tb_match_brackets.restype = ctypes.c_int
         L.tb_bbox_backward.argtypes = [P, P, P, I64, P, P, SZ, P, P]
         L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
@@ -268,6 +270,24 @@ def tb_compose(kind, xf, out=None, status=None):
     ws, wsb = workspace(OP_COMPOSE, n, 1, dev)
     _check(lib().tb_compose(_ptr(kind), _ptr(xf), n, _ptr(out), ctypes.c_void_p(ws), wsb,
                             _ptr(status), _stream()))
+    return out, status
+
+
+def tb_compose_f32(kind, xf, out=None, status=None):
+    """fp32 transforms composed down the tree in pointer-jumping order.
+    `xf` float32[n, 6] rows [a b c d e f] (rows of opens used).  Returns
+    (out float32[n, 6], status int32[1])."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    if xf.dtype != torch.float32 or xf.shape != (n, 6):
+        raise TypeError("xf must be float32 [n, 6]")
+    xf = xf.contiguous()
+    dev = kind.device
+    out = torch.empty((n, 6), dtype=torch.float32, device=dev) if out is None else out
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    ws, wsb = workspace(OP_COMPOSE_F32, n, 1, dev)
+    _check(lib().tb_compose_f32(_ptr(kind), _ptr(xf), n, _ptr(out), ctypes.c_void_p(ws), wsb,
+                                _ptr(status), _stream()))
     return out, status
 
 

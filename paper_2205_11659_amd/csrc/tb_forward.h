@@ -57,6 +57,17 @@ hipError_t brackets_run(const uint32_t *tok, int64_t n, int32_t *match, int32_t 
 hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *out, void *ws,
                        uint32_t *status, hipStream_t st);
 
+// fp32 transforms composed down the tree in pointer-jumping order: the
+// matching workspace, then pm, two pointer and two value buffers, flags.
+struct ComposeF32Layout {
+    FwdLayout f;
+    size_t pm, ptr0, ptr1, val0, val1, flags;
+    size_t total;
+};
+ComposeF32Layout compose_f32_layout(int64_t n);
+hipError_t compose_f32_run(const uint32_t *kind, const float *xf, int64_t n, float *out, void *ws,
+                           uint32_t *status, hipStream_t st);
+
 // Draw-object stream front end: the forward pipeline's workspace for n
 // elements (the extracted count is at most n), then the extracted arrays.
 struct StreamLayout {

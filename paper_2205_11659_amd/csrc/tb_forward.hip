@@ -1462,6 +1462,98 @@ __global__ void k_stream_match(const int32_t *__restrict__ cmatch,
     }
 }
 
+// --------------------------------------- fp32 transforms by pointer jumping
+// A monoid whose products round: 2-D affine transforms in fp32, composed
+// down the tree in the order of pointer jumping over the opens (section
+// "Parallel bounding boxes", Clips): each round every open replaces its
+// value v by (value at its pointer) . v and its pointer by the pointer's
+// pointer, all from the previous round's arrays.  Every product and every
+// sum rounds on its own (no fused multiply-add), in the order written in
+// f32_mul, so the result is defined bit for bit.
+struct F32Aff {
+    float a, b, c, d, e, f;
+};
+__device__ __forceinline__ F32Aff f32_id() { return {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f}; }
+// p . q (q applied first)
+__device__ __forceinline__ F32Aff f32_mul(const F32Aff &p, const F32Aff &q) {
+#pragma clang fp contract(off)
+    return {__fadd_rn(__fmul_rn(p.a, q.a), __fmul_rn(p.b, q.d)),
+            __fadd_rn(__fmul_rn(p.a, q.b), __fmul_rn(p.b, q.e)),
+            __fadd_rn(__fadd_rn(__fmul_rn(p.a, q.c), __fmul_rn(p.b, q.f)), p.c),
+            __fadd_rn(__fmul_rn(p.d, q.a), __fmul_rn(p.e, q.d)),
+            __fadd_rn(__fmul_rn(p.d, q.b), __fmul_rn(p.e, q.e)),
+            __fadd_rn(__fadd_rn(__fmul_rn(p.d, q.c), __fmul_rn(p.e, q.f)), p.f)};
+}
+// rows of 24 bytes, 8-byte aligned
+__device__ __forceinline__ F32Aff f32_ld(const float *base, int64_t i) {
+    const float2 *q = (const float2 *)base + 3 * i;
+    const float2 x = q[0], y = q[1], z = q[2];
+    return {x.x, x.y, y.x, y.y, z.x, z.y};
+}
+__device__ __forceinline__ void f32_st(float *base, int64_t i, const F32Aff &v) {
+    float2 *q = (float2 *)base + 3 * i;
+    q[0] = make_float2(v.a, v.b);
+    q[1] = make_float2(v.c, v.d);
+    q[2] = make_float2(v.e, v.f);
+}
+constexpr int XJ_ROUNDS = 32;  // flag words: flags[r] = 1 when round r+1 has work
+
+// every open: its own transform and a pointer to its enclosing open (pm);
+// other elements hold the identity and no pointer
+__global__ void k_xj_init(const uint32_t *__restrict__ kind, const float *__restrict__ xf,
+                          const int32_t *__restrict__ pm, int64_t n, float *__restrict__ val,
+                          int32_t *__restrict__ ptr, uint32_t *__restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool live = false;
+    if (i < n) {
+        const uint32_t k = kind[i];
+        const bool open = k == BCLIP || k == BBLEND;
+        const int32_t p = open ? pm[i] : -1;
+        f32_st(val, i, open ? f32_ld(xf, i) : f32_id());
+        ptr[i] = p;
+        live = p >= 0;
+    }
+    if (__ballot(live) && (threadIdx.x & (WAVE - 1)) == 0) flags[0] = 1u;  // every writer stores 1
+}
+
+// round r (>= 1): runs only if round r-1 left a pointer
+__global__ void k_xj_round(int r, const int32_t *__restrict__ ptr_in, const float *__restrict__ val_in,
+                           int32_t *__restrict__ ptr_out, float *__restrict__ val_out, int64_t n,
+                           uint32_t *__restrict__ flags) {
+    if (!flags[r - 1]) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool live = false;
+    if (i < n) {
+        const int32_t p = ptr_in[i];
+        F32Aff v = f32_ld(val_in, i);
+        int32_t np = -1;
+        if (p >= 0 && p < n) {
+            v = f32_mul(f32_ld(val_in, p), v);  // the enclosing part first
+            np = ptr_in[p];
+        }
+        f32_st(val_out, i, v);
+        ptr_out[i] = np;
+        live = np >= 0;
+    }
+    if (__ballot(live) && (threadIdx.x & (WAVE - 1)) == 0) flags[r] = 1u;
+}
+
+// results from the buffer the last executed round wrote: an open's own
+// value, a leaf's or close's the value of pm[i] (its enclosing or own open)
+__global__ void k_xj_out(const uint32_t *__restrict__ kind, const int32_t *__restrict__ pm,
+                         const float *__restrict__ val0, const float *__restrict__ val1, int64_t n,
+                         float *__restrict__ out, const uint32_t *__restrict__ flags, int rounds) {
+    int last = 0;
+    for (int r = 1; r <= rounds && flags[r - 1]; ++r) last = r;
+    const float *val = (last & 1) ? val1 : val0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = kind[i];
+    const int32_t p = pm[i];
+    const bool open = k == BCLIP || k == BBLEND;
+    f32_st(out, i, open ? f32_ld(val, i) : (p >= 0 && p < n) ? f32_ld(val, p) : f32_id());
+}
+
 // ----------------------------------------------------------------- driver
 hipEvent_t g_prof_before = nullptr, g_prof_after = nullptr;
 
@@ -1717,6 +1809,50 @@ hipError_t brackets_run(const uint32_t *tok, int64_t n, int32_t *match, int32_t 
     if (n == 0) return hipGetLastError();
     return run_pipeline<false, Box, SinkOut, true>(tok, nullptr, n, nullptr, 1, match, pm, SinkOut{nullptr},
                                                    w, L, status, st, nullptr, var);
+}
+
+ComposeF32Layout compose_f32_layout(int64_t n) {
+    ComposeF32Layout C{};
+    C.f = fwd_layout(n, 1, sizeof(Box), false);
+    const int64_t nn = n > 0 ? n : 1;
+    size_t o = C.f.total;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += al(bytes);
+        return r;
+    };
+    C.pm = take(sizeof(int32_t) * nn);
+    C.ptr0 = take(sizeof(int32_t) * nn);
+    C.ptr1 = take(sizeof(int32_t) * nn);
+    C.val0 = take(24 * (size_t)nn);
+    C.val1 = take(24 * (size_t)nn);
+    C.flags = take(sizeof(uint32_t) * XJ_ROUNDS);
+    C.total = o;
+    return C;
+}
+
+hipError_t compose_f32_run(const uint32_t *kind, const float *xf, int64_t n, float *out, void *ws,
+                           uint32_t *status, hipStream_t st) {
+    const ComposeF32Layout C = compose_f32_layout(n);
+    char *w = (char *)ws;
+    int32_t *pm = (int32_t *)(w + C.pm);
+    // the enclosing open of every element: matching's stronger output (Fig. 1)
+    hipError_t e = fwd_run(false, kind, nullptr, n, nullptr, 1, nullptr, pm, nullptr, ws, status, st,
+                           default_variant(false));
+    if (e != hipSuccess || n == 0) return e;
+    int32_t *ptr[2] = {(int32_t *)(w + C.ptr0), (int32_t *)(w + C.ptr1)};
+    float *val[2] = {(float *)(w + C.val0), (float *)(w + C.val1)};
+    uint32_t *flags = (uint32_t *)(w + C.flags);
+    int rounds = 0;  // depth < n, so ceil(log2 n) rounds always suffice
+    while (((int64_t)1 << rounds) < n) ++rounds;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    k_zero_status<<<1, XJ_ROUNDS, 0, st>>>(flags, XJ_ROUNDS, flags);
+    k_xj_init<<<g, 256, 0, st>>>(kind, xf, pm, n, val[0], ptr[0], flags);
+    for (int r = 1; r <= rounds; ++r)
+        k_xj_round<<<g, 256, 0, st>>>(r, ptr[(r - 1) & 1], val[(r - 1) & 1], ptr[r & 1], val[r & 1], n,
+                                       flags);
+    k_xj_out<<<g, 256, 0, st>>>(kind, pm, val[0], val[1], n, out, flags, rounds);
+    return hipGetLastError();
 }
 
 hipError_t fwd_run_noalloc(const uint32_t *kind, const float4 *box, int64_t n, int32_t *match,

@@ -17,7 +17,7 @@ TB_OK, TB_ERR_NULL, TB_ERR_SIZE, TB_ERR_ALIGN, TB_ERR_WORKSPACE, TB_ERR_ARG, TB_
 def declared_functions():
     text = open(HDR).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tb_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tb_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -31,7 +31,8 @@ def lib():
 def test_header_declares_the_four_calls():
     fns = declared_functions()
     for f in ("tb_match", "tb_bbox", "tb_bbox_backward", "tb_bbox_batched", "tb_compose",
-              "tb_bbox_stream",
+              "tb_bbox_stream", "tb_compose_f32", "tb_match_brackets", "tb_bbox_noalloc",
+              "tb_tune_bbox", "tb_variant_get",
               "tb_workspace_bytes", "tb_status_str"):
         assert f in fns
 
@@ -45,7 +46,7 @@ def test_workspace_bytes(lib):
     f = lib.tb_workspace_bytes
     f.restype = ctypes.c_size_t
     f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
-    for op in (0, 1, 2, 3, 4, 5):
+    for op in (0, 1, 2, 3, 4, 5, 6):
         assert f(op, 0, 1) > 0
         a, b = f(op, 1000, 1), f(op, 1 << 20, 1)
         assert 0 < a < b

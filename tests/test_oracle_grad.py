@@ -264,3 +264,64 @@ def test_grad_range_status():
     g2[1] = np.nan
     _, st = oracle.backward(kind2, box2, g2)
     assert st == 0
+
+
+def test_finite_differences_on_the_16m_gradient_scene():
+    """The FP64 central-difference check on 512 coordinates of the 2^24
+    gradient scene itself (cap 256, 2^-8 grid, N(0,1) upstream gradient),
+    against the exact rational gradient that the oracle's routing gives, to
+    1e-9 relative.  A perturbation of one input coordinate changes only rows
+    of the top-level subtree holding it (the root context is the whole
+    plane and no union crosses depth 0), so each central difference runs
+    the fp64 walk on that subtree alone; coordinates are drawn by seed from
+    those whose subtree has at most 2^20 elements, and, as in the smaller
+    check, ties (one-sided derivatives that differ) are redrawn."""
+    c = gen.config(4)
+    kind, box, g = c["kind"], c["box"], c["grad"]
+    n = len(kind)
+    src, st = oracle.sources(kind, box)
+    assert st == 0
+    depth = np.cumsum(np.where(np.isin(kind, (1, 3)), 1, np.where(np.isin(kind, (2, 4)), -1, 0)))
+    starts = np.concatenate([[0], np.flatnonzero(depth[:-1] == 0) + 1])  # top-level subtrees
+    seg_of = np.searchsorted(starts, np.arange(n), side="right") - 1
+    seg_end = np.append(starts[1:], n)
+    flat = src.reshape(-1)
+    routed = np.flatnonzero(flat >= 0)
+    order = routed[np.argsort(flat[routed] * 4 + routed % 4, kind="stable")]  # by (source, coordinate)
+    keys = flat[order] * 4 + order % 4
+    h = 2.0 ** -10
+    rng = np.random.default_rng(0x4FD)
+    cand = np.unique(keys)
+    done = nonzero = tried = 0
+    while done < 512:
+        tried += 1
+        assert tried < 20000
+        key = int(cand[int(rng.integers(0, len(cand)))])
+        e, cc = divmod(key, 4)
+        a, b = int(starts[seg_of[e]]), int(seg_end[seg_of[e]])
+        if b - a > (1 << 20):
+            continue
+        kk, bb = kind[a:b], box[a:b].astype(np.float64)
+        base, _ = oracle.bbox_f64(kk, bb)
+        outs = {}
+        for step in (h, -h, h / 2, -h / 2):
+            b2 = bb.copy()
+            b2[e - a, cc] += step
+            outs[step], _ = oracle.bbox_f64(kk, b2)
+        fin = np.isfinite(base)
+        if not (np.array_equal(np.isfinite(outs[h]), fin) and np.array_equal(np.isfinite(outs[-h]), fin)):
+            continue
+        with np.errstate(invalid="ignore"):
+            d1, d2, d3 = (outs[h] - base)[fin], (base - outs[-h])[fin], (outs[h / 2] - base)[fin]
+        if not (np.array_equal(d1, d2) and np.array_equal(d1, 2 * d3) and np.isin(d1, [0.0, h, -h]).all()):
+            continue  # a tie
+        fd = float(np.sum(g[a:b].astype(np.float64)[fin] * (outs[h][fin] - outs[-h][fin]))) / (2 * h)
+        lo, hi = np.searchsorted(keys, key), np.searchsorted(keys, key, side="right")
+        exact = float(sum(Fraction(float(g.reshape(-1)[r])) for r in order[lo:hi]))
+        if exact == 0.0:
+            assert abs(fd) <= 1e-12
+        else:
+            nonzero += 1
+            assert abs(fd - exact) <= 1e-9 * abs(exact), (e, cc, fd, exact)
+        done += 1
+    assert nonzero > 400
