@@ -266,6 +266,19 @@ def batched_section(steps, warmup, cpu=False):
     tuned = tb.tune_bbox_batched(kind, box, off, reps=3)[0] if TUNE else None
     ms_b = time_steps(lambda: tb.tb_bbox_batched(kind, box, off), steps, warmup)
     bout, bm, bst = tb.tb_bbox_batched(kind, box, off)
+    # the same batched call captured once in a HIP graph and replayed (the
+    # paper excludes launch overhead; so does this figure)
+    bo2 = torch.empty_like(bout)
+    bm2 = torch.empty_like(bm)
+    bs2 = torch.empty_like(bst)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    bgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(bgraph, stream=side):
+            tb.tb_bbox_batched_into(kind, box, off, bm2, bo2, bs2)
+    torch.cuda.current_stream().wait_stream(side)
+    ms_bg = time_steps(bgraph.replay, steps, warmup)
     g = tb.PerSceneGraph(kind, box, c["offsets"])
     ms_g = time_steps(g.replay, steps, warmup)
     gout, gm, gst = g.replay()
@@ -274,6 +287,9 @@ def batched_section(steps, warmup, cpu=False):
                 and int(bst.abs().sum()) == 0 and int(gst.abs().sum()) == 0)
     out.update({"workload": "batch-2048-ragged", "elements": n, "scenes": len(c["offsets"]) - 1,
                 "batched_ms": round(ms_b, 4), "batched_gelem_s": round(n / ms_b / 1e6, 3),
+                "batched_graph_ms": round(ms_bg, 4), "batched_graph_gelem_s": round(n / ms_bg / 1e6, 3),
+                "graph_identical": bool(torch.equal(bo2.view(torch.int32), bout.view(torch.int32))
+                                        and torch.equal(bm2, bm)),
                 "per_scene_graph_ms": round(ms_g, 4), "per_scene_graph_gelem_s": round(n / ms_g / 1e6, 3),
                 "speedup": round(ms_g / ms_b, 3), "byte_identical": same,
                 "autotune": _tune_record(tuned) if tuned else None})
@@ -409,6 +425,30 @@ def compose_f32_section(steps, warmup):
             "hbm_frac_alg": round(52 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def reduce_up_f32_section(steps, warmup):
+    """tb_reduce_up_f32 (leaves' fp32 transforms multiplied up the tree,
+    segment-tree grouping) on the 2^24 cap-256 walk; algorithmic bytes:
+    kind 4 + transform 24 in, transform 24 out per element."""
+    import torch
+
+    import gen
+    import paper_2205_11659_amd as tb
+    c = gen.config(4)
+    n = len(c["kind"])
+    kind = torch.from_numpy(c["kind"].view(np.int32)).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(gen.SEED_BASE + 41)
+    xf = torch.rand((n, 6), generator=g, device="cuda") * 2 - 1
+    out = torch.empty_like(xf)
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    ms = time_steps(lambda: tb.tb_reduce_up_f32(kind, xf, out=out, status=st), steps, warmup)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return {"workload": "scene-16M-cap256", "elements": n, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n / ms / 1e6, 3),
+            "hbm_frac_alg": round(52 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def stream_section(steps, warmup):
     """tb_bbox_stream on a draw-object stream of 2^27 elements holding a
     cap-64 random-walk tree of 2^24 elements (density 1/8).  Algorithmic
@@ -456,7 +496,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="time the default launch variant")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd sections")
     ap.add_argument("--only", choices=["stream", "match", "compose", "batched", "fwd_bwd", "small",
-                                       "c1", "copy", "brackets", "compose_f32"],
+                                       "c1", "copy", "brackets", "compose_f32", "reduce_up_f32"],
                     help="run one secondary section alone and print its JSON (for profiling)")
     args = ap.parse_args()
     global TUNE
@@ -469,6 +509,7 @@ def main():
         fn = {"stream": stream_section, "match": match_section, "compose": compose_section,
               "batched": batched_section, "fwd_bwd": fwd_bwd_section, "c1": c1_section,
               "brackets": brackets_section, "compose_f32": compose_f32_section,
+              "reduce_up_f32": reduce_up_f32_section,
               "small": lambda st, w: small_section(),
               "copy": lambda st, w: copy_ceiling(max(st, 1))}[args.only]
         print(json.dumps({args.only: fn(args.steps, args.warmup)}), flush=True)
@@ -559,6 +600,7 @@ def main():
         torch.cuda.empty_cache()
         res["brackets"] = brackets_section(max(3, args.steps // 2), 2)
         res["compose_f32"] = compose_f32_section(max(3, args.steps // 2), 2)
+        res["reduce_up_f32"] = reduce_up_f32_section(max(3, args.steps // 2), 2)
         res["stream"] = stream_section(max(3, args.steps // 2), 2)
         torch.cuda.empty_cache()
         res["batched_vs_per_scene"] = batched_section(max(3, args.steps // 2), 2, cpu=not args.no_cpu)

@@ -103,6 +103,7 @@ typedef enum {
 #define TB_OP_COMPOSE 4
 #define TB_OP_BBOX_STREAM 5
 #define TB_OP_COMPOSE_F32 6
+#define TB_OP_REDUCE_UP_F32 7
 
 /* Workspace bytes needed by `op` for n elements (num_scenes is used by
    TB_OP_BBOX_BATCHED only; pass 1 otherwise).  Returns 0 for invalid sizes. */
@@ -248,6 +249,27 @@ tb_status tb_compose(const uint32_t *kind, const tb_affine *xf_in, int64_t n, tb
  */
 tb_status tb_compose_f32(const uint32_t *kind, const float *xf_in, int64_t n, float *xf_out, void *ws,
                          size_t ws_bytes, uint32_t *dev_status, void *stream);
+
+/*
+ * The other direction with a rounding monoid: the fp32 transforms of the
+ * leaves multiplied UP the tree (the Introduction states the method for
+ * general monoids; blend unions are the paper's case going up).  An open
+ * and its close get the ordered product of the transforms of the leaves
+ * strictly between them, the leftmost leaf the leftmost factor (p . q as
+ * in tb_compose_f32); an open with no leaf inside gets the identity; a leaf
+ * gets its own transform.  The grouping is a segment tree over positions:
+ * with N the smallest power of two >= n, leaf node N+i holds element i's
+ * transform if it is a leaf, node v = node 2v . node 2v+1 (a side with no
+ * leaf leaves the other unchanged), and the range of leaves is read
+ * bottom-up (l = lo+N, r = hi+N+1; while l < r: if l odd L = L . node[l++];
+ * if r odd R = node[--r] . R; l /= 2; r /= 2), result L . R.  Inputs must be
+ * finite.  Rows of leaf inputs are used.
+ *   kind, xf_in, xf_out, dev_status: as tb_compose_f32
+ * Workspace: tb_workspace_bytes(TB_OP_REDUCE_UP_F32, n, 1) (48 B per
+ * element of 2N tree nodes, plus matching).
+ */
+tb_status tb_reduce_up_f32(const uint32_t *kind, const float *xf_in, int64_t n, float *xf_out, void *ws,
+                           size_t ws_bytes, uint32_t *dev_status, void *stream);
 
 /*
  * Node boxes over a draw-object stream (Introduction: a renderer extracts

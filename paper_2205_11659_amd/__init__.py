@@ -24,7 +24,8 @@ DATA_BAD_KIND, DATA_UNBALANCED, DATA_KIND_MISMATCH, DATA_BAD_OFFSETS, DATA_GRAD_
 _DATA_NAMES = {DATA_BAD_KIND: "BAD_KIND", DATA_UNBALANCED: "UNBALANCED",
                DATA_KIND_MISMATCH: "KIND_MISMATCH", DATA_BAD_OFFSETS: "BAD_OFFSETS",
                DATA_GRAD_RANGE: "GRAD_RANGE"}
-OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE, OP_BBOX_STREAM, OP_COMPOSE_F32 = range(7)
+(OP_MATCH, OP_BBOX, OP_BBOX_BACKWARD, OP_BBOX_BATCHED, OP_COMPOSE, OP_BBOX_STREAM, OP_COMPOSE_F32,
+ OP_REDUCE_UP_F32) = range(8)
 
 _lib = None
 
@@ -48,6 +49,8 @@ def lib():
         L.tb_match_brackets.argtypes = [P, I64, P, P, P, SZ, P, P]
         L.tb_compose_f32.argtypes = [P, P, I64, P, P, SZ, P, P]
         L.tb_compose_f32.restype = ctypes.c_int
+        L.tb_reduce_up_f32.argtypes = [P, P, I64, P, P, SZ, P, P]
+        L.tb_reduce_up_f32.restype = ctypes.c_int
         L.tb_match_brackets.restype = ctypes.c_int
         L.tb_bbox_backward.argtypes = [P, P, P, I64, P, P, SZ, P, P]
         L.tb_bbox_batched.argtypes = [P, P, P, I64, I64, P, P, P, SZ, P, P]
@@ -240,6 +243,19 @@ def tb_bbox_batched(kind, box, offsets, match=True):
     return out, m, status
 
 
+def tb_bbox_batched_into(kind, box, offsets, match, out, status):
+    """tb_bbox_batched into the caller's preallocated match (or None), out
+    and status (S words) tensors: nothing is allocated here except a larger
+    cached workspace on first use, so it can be captured in a HIP graph."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    S = offsets.numel() - 1
+    ws, wsb = workspace(OP_BBOX_BATCHED, n, S, kind.device)
+    _check(lib().tb_bbox_batched(_ptr(kind), _ptr(box), _ptr(offsets), S, n, _ptr(match), _ptr(out),
+                                 ctypes.c_void_p(ws), wsb, _ptr(status), _stream()))
+    return out, match, status
+
+
 def tb_bbox_backward(kind, box, grad_out):
     """Gradient of tb_bbox's box output w.r.t. box: returns (grad_in, status)."""
     kind = _as_kind(kind)
@@ -288,6 +304,24 @@ def tb_compose_f32(kind, xf, out=None, status=None):
     ws, wsb = workspace(OP_COMPOSE_F32, n, 1, dev)
     _check(lib().tb_compose_f32(_ptr(kind), _ptr(xf), n, _ptr(out), ctypes.c_void_p(ws), wsb,
                                 _ptr(status), _stream()))
+    return out, status
+
+
+def tb_reduce_up_f32(kind, xf, out=None, status=None):
+    """fp32 transforms of the leaves multiplied up the tree in sequence order
+    (segment-tree grouping).  `xf` float32[n, 6] (rows of leaves used).
+    Returns (out float32[n, 6], status int32[1])."""
+    kind = _as_kind(kind)
+    n = kind.numel()
+    if xf.dtype != torch.float32 or xf.shape != (n, 6):
+        raise TypeError("xf must be float32 [n, 6]")
+    xf = xf.contiguous()
+    dev = kind.device
+    out = torch.empty((n, 6), dtype=torch.float32, device=dev) if out is None else out
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    ws, wsb = workspace(OP_REDUCE_UP_F32, n, 1, dev)
+    _check(lib().tb_reduce_up_f32(_ptr(kind), _ptr(xf), n, _ptr(out), ctypes.c_void_p(ws), wsb,
+                                  _ptr(status), _stream()))
     return out, status
 
 

@@ -29,6 +29,8 @@ size_t ws_bytes_for(int op, int64_t n, int64_t S) {
         return tb::stream_layout(n).total;
     case TB_OP_COMPOSE_F32:
         return tb::compose_f32_layout(n).total;
+    case TB_OP_REDUCE_UP_F32:
+        return tb::reduce_up_layout(n).total;
     default:
         return 0;
     }
@@ -114,6 +116,17 @@ tb_status tb_compose_f32(const uint32_t *kind, const float *xf_in, int64_t n, fl
     tb_status c = check_common(kind, n, ws, ws_bytes, TB_OP_COMPOSE_F32, 1);
     if (c != TB_OK) return c;
     return launched(tb::compose_f32_run(kind, xf_in, n, xf_out, ws, dev_status, (hipStream_t)stream));
+}
+
+tb_status tb_reduce_up_f32(const uint32_t *kind, const float *xf_in, int64_t n, float *xf_out, void *ws,
+                           size_t ws_bytes, uint32_t *dev_status, void *stream) {
+    if (n < 0 || n >= MAX_N) return TB_ERR_SIZE;
+    if (!dev_status || (n > 0 && (!xf_in || !xf_out))) return TB_ERR_NULL;
+    if (!aligned(dev_status, 4) || (xf_in && !aligned(xf_in, 8)) || (xf_out && !aligned(xf_out, 8)))
+        return TB_ERR_ALIGN;
+    tb_status c = check_common(kind, n, ws, ws_bytes, TB_OP_REDUCE_UP_F32, 1);
+    if (c != TB_OK) return c;
+    return launched(tb::reduce_up_run(kind, xf_in, n, xf_out, ws, dev_status, (hipStream_t)stream));
 }
 
 tb_status tb_bbox_stream(const uint32_t *tag, const tb_box *box_in, int64_t n, int32_t *match,

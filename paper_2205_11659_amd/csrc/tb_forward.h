@@ -68,6 +68,18 @@ ComposeF32Layout compose_f32_layout(int64_t n);
 hipError_t compose_f32_run(const uint32_t *kind, const float *xf, int64_t n, float *out, void *ws,
                            uint32_t *status, hipStream_t st);
 
+// fp32 transforms of the leaves multiplied up the tree (segment-tree
+// grouping): the matching workspace, the partners, the 2N tree nodes.
+struct ReduceUpLayout {
+    FwdLayout f;
+    int64_t N;
+    size_t match, node;
+    size_t total;
+};
+ReduceUpLayout reduce_up_layout(int64_t n);
+hipError_t reduce_up_run(const uint32_t *kind, const float *xf, int64_t n, float *out, void *ws,
+                         uint32_t *status, hipStream_t st);
+
 // Draw-object stream front end: the forward pipeline's workspace for n
 // elements (the extracted count is at most n), then the extracted arrays.
 struct StreamLayout {

@@ -378,11 +378,21 @@ __global__ void k_jump(const int32_t *__restrict__ ptr_in, const void *__restric
                        int32_t *__restrict__ ptr_out, void *__restrict__ val_out, int64_t M) {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= M) return;
+    // Two hops per round (3^r partitions after r rounds, so fewer launches):
+    // the value two owners up, then one owner up, then this partition's, in
+    // ancestor-first order.
     int32_t p = ptr_in[P];
     V v = Pay<V>::ld(val_in, P);
     if (p >= 0) {
-        v = isect(Pay<V>::ld(val_in, p), v);  // ancestor first
-        p = ptr_in[p];
+        const int32_t pp = ptr_in[p];
+        const V vp = Pay<V>::ld(val_in, p);
+        if (pp >= 0) {
+            v = isect(Pay<V>::ld(val_in, pp), isect(vp, v));
+            p = ptr_in[pp];
+        } else {
+            v = isect(vp, v);
+            p = -1;
+        }
     }
     ptr_out[P] = p;
     Pay<V>::st(val_out, P, v);
@@ -1256,6 +1266,11 @@ struct SinkGrad {
     }
 };
 
+__global__ void k_zero_u64(unsigned long long *p, int64_t cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = 0ull;
+}
+
 // grad_in = RNE_fp32(acc + own q(g)) * 2^-32; the integer sums wrap modulo
 // 2^64, so only the final sum has to fit in an int64
 __global__ void k_grad_final(const float4 *__restrict__ g, const unsigned long long *__restrict__ acc,
@@ -1276,10 +1291,6 @@ __global__ void k_grad_final(const float4 *__restrict__ g, const unsigned long l
     gin[i] = make_float4(r[0], r[1], r[2], r[3]);
 }
 
-__global__ void k_zero_u64(unsigned long long *p, int64_t cnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) p[i] = 0ull;
-}
 
 // ------------------------------------------------- draw-object stream front end
 // The tree's elements (tags 0..4) are extracted from a stream that also
@@ -1554,6 +1565,68 @@ __global__ void k_xj_out(const uint32_t *__restrict__ kind, const int32_t *__res
     f32_st(out, i, open ? f32_ld(val, i) : (p >= 0 && p < n) ? f32_ld(val, p) : f32_id());
 }
 
+// ------------------------------- fp32 transforms multiplied up the tree
+// Every open (and its close) gets the ordered product of the transforms of
+// the leaves strictly between them, leftmost leaf leftmost.  Products round,
+// so the grouping is fixed by a segment tree over positions: leaf node N+i
+// holds element i's transform if it is a leaf, node v = node 2v . node 2v+1
+// (a side without leaves leaves the other unchanged), and a range is read
+// bottom-up, left boundary nodes folded left to right, right boundary nodes
+// right to left, then the two joined.  A node without leaves holds NONE, a
+// NaN bit pattern no finite input or fp32 operation produces.
+constexpr uint32_t UP_NONE = 0xFFFFFFFFu;
+__device__ __forceinline__ bool up_none(const F32Aff &v) { return __float_as_uint(v.a) == UP_NONE; }
+__device__ __forceinline__ F32Aff up_none_val() {
+    const float x = __uint_as_float(UP_NONE);
+    return {x, x, x, x, x, x};
+}
+__device__ __forceinline__ F32Aff up_comb(const F32Aff &a, const F32Aff &b) {
+    return up_none(a) ? b : up_none(b) ? a : f32_mul(a, b);
+}
+
+__global__ void k_up_leaves(const uint32_t *__restrict__ kind, const float *__restrict__ xf, int64_t n,
+                            int64_t N, float *__restrict__ node) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    f32_st(node, N + i, (i < n && kind[i] == LEAF) ? f32_ld(xf, i) : up_none_val());
+}
+
+// nodes [h, 2h) from their children
+__global__ void k_up_level(int64_t h, float *__restrict__ node) {
+    const int64_t v = h + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= 2 * h) return;
+    f32_st(node, v, up_comb(f32_ld(node, 2 * v), f32_ld(node, 2 * v + 1)));
+}
+
+__global__ void k_up_query(const uint32_t *__restrict__ kind, const float *__restrict__ xf,
+                           const int32_t *__restrict__ match, int64_t n, int64_t N,
+                           const float *__restrict__ node, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = kind[i];
+    const int64_t m = match[i];
+    if (k == LEAF) {
+        f32_st(out, i, f32_ld(xf, i));
+        return;
+    }
+    if (!is_open(k) || m <= i || m >= n) {
+        if (!(is_close(k) && m >= 0 && m < i)) f32_st(out, i, f32_id());  // malformed: unspecified
+        return;
+    }
+    F32Aff L = up_none_val(), R = up_none_val();
+    int64_t l = i + 1 + N, r = m + N;  // leaves (i, m): [i+1, m-1]
+    while (l < r) {
+        if (l & 1) L = up_comb(L, f32_ld(node, l++));
+        if (r & 1) R = up_comb(f32_ld(node, --r), R);
+        l >>= 1;
+        r >>= 1;
+    }
+    F32Aff q = up_comb(L, R);
+    if (up_none(q)) q = f32_id();
+    f32_st(out, i, q);
+    f32_st(out, m, q);
+}
+
 // ----------------------------------------------------------------- driver
 hipEvent_t g_prof_before = nullptr, g_prof_after = nullptr;
 
@@ -1672,7 +1745,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     } else {
         k_spine_link<BOXES, V><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
         if (BOXES) {
-            for (int r = 0; r < rounds; ++r) {
+            for (int64_t reach = 1; reach < M; reach *= 3) {  // reach: owners covered so far
                 k_jump<V><<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
                 cur ^= 1;
             }
@@ -1852,6 +1925,41 @@ hipError_t compose_f32_run(const uint32_t *kind, const float *xf, int64_t n, flo
         k_xj_round<<<g, 256, 0, st>>>(r, ptr[(r - 1) & 1], val[(r - 1) & 1], ptr[r & 1], val[r & 1], n,
                                        flags);
     k_xj_out<<<g, 256, 0, st>>>(kind, pm, val[0], val[1], n, out, flags, rounds);
+    return hipGetLastError();
+}
+
+ReduceUpLayout reduce_up_layout(int64_t n) {
+    ReduceUpLayout U{};
+    U.f = fwd_layout(n, 1, sizeof(Box), false);
+    int64_t N = 1;
+    while (N < n) N <<= 1;
+    U.N = N;
+    size_t o = U.f.total;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += al(bytes);
+        return r;
+    };
+    U.match = take(sizeof(int32_t) * (n > 0 ? n : 1));
+    U.node = take(24 * (size_t)(2 * N));
+    U.total = o;
+    return U;
+}
+
+hipError_t reduce_up_run(const uint32_t *kind, const float *xf, int64_t n, float *out, void *ws,
+                         uint32_t *status, hipStream_t st) {
+    const ReduceUpLayout U = reduce_up_layout(n);
+    char *w = (char *)ws;
+    int32_t *match = (int32_t *)(w + U.match);
+    hipError_t e = fwd_run(false, kind, nullptr, n, nullptr, 1, match, nullptr, nullptr, ws, status, st,
+                           default_variant(false));
+    if (e != hipSuccess || n == 0) return e;
+    float *node = (float *)(w + U.node);
+    const int64_t N = U.N;
+    k_up_leaves<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(kind, xf, n, N, node);
+    for (int64_t h = N / 2; h >= 1; h /= 2)
+        k_up_level<<<(unsigned)((h + 255) / 256), 256, 0, st>>>(h, node);
+    k_up_query<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(kind, xf, match, n, N, node, out);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ def test_workspace_bytes(lib):
     f = lib.tb_workspace_bytes
     f.restype = ctypes.c_size_t
     f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
-    for op in (0, 1, 2, 3, 4, 5, 6):
+    for op in (0, 1, 2, 3, 4, 5, 6, 7):
         assert f(op, 0, 1) > 0
         a, b = f(op, 1000, 1), f(op, 1 << 20, 1)
         assert 0 < a < b
