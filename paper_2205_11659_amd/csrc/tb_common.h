@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace tb {
 
 // Partition geometry: one workgroup of W threads handles T = W*K consecutive
@@ -80,6 +82,21 @@ __device__ __forceinline__ BoxS canon(BoxS a) {
     return {INFINITY, INFINITY, -INFINITY, -INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
 }
 
+template <class V>
+__device__ __forceinline__ V vsel(bool c, const V &a, const V &b) {
+    return c ? a : b;
+}
+// Component-wise select.  A conditional expression on two payload lvalues
+// is a select of their addresses, which can keep the payloads in scratch
+// memory; this builds the result from selected scalars instead.
+__device__ __forceinline__ Box vsel(bool c, const Box &a, const Box &b) {
+    return {c ? a.x0 : b.x0, c ? a.y0 : b.y0, c ? a.x1 : b.x1, c ? a.y1 : b.y1};
+}
+__device__ __forceinline__ BoxS vsel(bool c, const BoxS &a, const BoxS &b) {
+    return {c ? a.x0 : b.x0, c ? a.y0 : b.y0, c ? a.x1 : b.x1, c ? a.y1 : b.y1,
+            c ? a.s0 : b.s0, c ? a.s1 : b.s1, c ? a.s2 : b.s2, c ? a.s3 : b.s3};
+}
+
 // Payload traits: identities, own element, workspace load/store.
 template <class V>
 struct Pay;
@@ -147,6 +164,9 @@ __device__ __forceinline__ Aff isect(const Aff &p, const Aff &q) {
 // there is nothing to combine upwards; the union steps are compiled out
 __device__ __forceinline__ Aff unite(Aff a, const Aff &) { return a; }
 __device__ __forceinline__ Aff canon(Aff a) { return a; }
+__device__ __forceinline__ Aff vsel(bool c, const Aff &a, const Aff &b) {
+    return {c ? a.a : b.a, c ? a.b : b.b, c ? a.c : b.c, c ? a.d : b.d, c ? a.e : b.e, c ? a.f : b.f};
+}
 template <>
 struct Pay<Aff> {
     static constexpr bool kUnions = false;
@@ -299,11 +319,77 @@ __device__ __forceinline__ BicR shfl_idx(BicR x, int src) {
 }
 __device__ __forceinline__ int shfl_idx(int x, int src) { return __shfl(x, src, WAVE); }
 
+// Box min/max steps as DPP-modified VALU ops: each component is combined
+// with its DPP source lane in one instruction (the compiler forms this only
+// for integer ops).  Lanes without a source keep their value, which is the
+// identity behaviour for these idempotent combines.  The leading s_nop covers
+// the wait states a DPP read needs after a VALU write of its source or of
+// EXEC; inside a block every component is written three instructions before
+// its next DPP read.
+#define TB_DPP4(OA, OB, CTRL)                                                                          \
+    OA " %0, %0, %0 " CTRL "\n\t" OA " %1, %1, %1 " CTRL "\n\t" OB " %2, %2, %2 " CTRL "\n\t" OB \
+       " %3, %3, %3 " CTRL "\n\t"
+#define TB_DPP_UNITE(CTRL) TB_DPP4("v_min_f32_dpp", "v_max_f32_dpp", CTRL)
+#define TB_DPP_ISECT(CTRL) TB_DPP4("v_max_f32_dpp", "v_min_f32_dpp", CTRL)
+#define TB_BOX_OPS(b) "+v"(b.x0), "+v"(b.y0), "+v"(b.x1), "+v"(b.y1)
+// one scan step (row_shr 1, 2, 4, 8, then row_bcast 15 and 31), unite
+template <int STEP>
+__device__ __forceinline__ void box_unite_step(Box &b) {
+    if constexpr (STEP == 0) asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_shr:1 row_mask:0xf bank_mask:0xf") : TB_BOX_OPS(b));
+    if constexpr (STEP == 1) asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_shr:2 row_mask:0xf bank_mask:0xf") : TB_BOX_OPS(b));
+    if constexpr (STEP == 2) asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_shr:4 row_mask:0xf bank_mask:0xf") : TB_BOX_OPS(b));
+    if constexpr (STEP == 3) asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_shr:8 row_mask:0xf bank_mask:0xf") : TB_BOX_OPS(b));
+    if constexpr (STEP == 4) asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_bcast:15 row_mask:0xa bank_mask:0xf") : TB_BOX_OPS(b));
+    if constexpr (STEP == 5) asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_bcast:31 row_mask:0xc bank_mask:0xf") : TB_BOX_OPS(b));
+}
+// the six steps of an inclusive wave scan in one block
+template <bool UNITE>
+__device__ __forceinline__ void box_incl_scan_dpp(Box &b) {
+    if constexpr (UNITE)
+        asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_shr:1 row_mask:0xf bank_mask:0xf")
+                         TB_DPP_UNITE("row_shr:2 row_mask:0xf bank_mask:0xf")
+                             TB_DPP_UNITE("row_shr:4 row_mask:0xf bank_mask:0xf")
+                                 TB_DPP_UNITE("row_shr:8 row_mask:0xf bank_mask:0xf")
+                                     TB_DPP_UNITE("row_bcast:15 row_mask:0xa bank_mask:0xf")
+                                         TB_DPP_UNITE("row_bcast:31 row_mask:0xc bank_mask:0xf") "s_nop 1"
+                     : TB_BOX_OPS(b));
+    else
+        asm volatile("s_nop 4\n\t" TB_DPP_ISECT("row_shr:1 row_mask:0xf bank_mask:0xf")
+                         TB_DPP_ISECT("row_shr:2 row_mask:0xf bank_mask:0xf")
+                             TB_DPP_ISECT("row_shr:4 row_mask:0xf bank_mask:0xf")
+                                 TB_DPP_ISECT("row_shr:8 row_mask:0xf bank_mask:0xf")
+                                     TB_DPP_ISECT("row_bcast:15 row_mask:0xa bank_mask:0xf")
+                                         TB_DPP_ISECT("row_bcast:31 row_mask:0xc bank_mask:0xf") "s_nop 1"
+                     : TB_BOX_OPS(b));
+}
+// in-row suffix steps (lane i combines lane i + 1, 2, 4, 8 of its row)
+template <bool UNITE>
+__device__ __forceinline__ void box_suffix_rows_dpp(Box &b) {
+    if constexpr (UNITE)
+        asm volatile("s_nop 4\n\t" TB_DPP_UNITE("row_shl:1 row_mask:0xf bank_mask:0xf")
+                         TB_DPP_UNITE("row_shl:2 row_mask:0xf bank_mask:0xf")
+                             TB_DPP_UNITE("row_shl:4 row_mask:0xf bank_mask:0xf")
+                                 TB_DPP_UNITE("row_shl:8 row_mask:0xf bank_mask:0xf") "s_nop 1"
+                     : TB_BOX_OPS(b));
+    else
+        asm volatile("s_nop 4\n\t" TB_DPP_ISECT("row_shl:1 row_mask:0xf bank_mask:0xf")
+                         TB_DPP_ISECT("row_shl:2 row_mask:0xf bank_mask:0xf")
+                             TB_DPP_ISECT("row_shl:4 row_mask:0xf bank_mask:0xf")
+                                 TB_DPP_ISECT("row_shl:8 row_mask:0xf bank_mask:0xf") "s_nop 1"
+                     : TB_BOX_OPS(b));
+}
+template <class V, class Op>
+constexpr bool kBoxDpp = std::is_same<V, Box>::value && (std::is_same<Op, UniteOp>::value || std::is_same<Op, IsectOp>::value);
+
 // Inclusive scan inside one wave for an associative `op` with identity `id`
 // (operands in lane order): in-row steps of 1, 2, 4, 8 lanes, then the row
 // totals are carried across rows 0->1, 2->3 and 1->2,3.
 template <class V, class Op>
 __device__ __forceinline__ V wave_incl_scan(V v, Op op, V id) {
+    if constexpr (kBoxDpp<V, Op>) {
+        box_incl_scan_dpp<std::is_same<Op, UniteOp>::value>(v);
+        return v;
+    }
     v = op(dmov<dpp::SHR1>(id, v), v);
     v = op(dmov<dpp::SHR2>(id, v), v);
     v = op(dmov<dpp::SHR4>(id, v), v);
@@ -325,23 +411,28 @@ __device__ __forceinline__ V wave_excl_scan(V v, Op op, V ident, V *total) {
 // in lane order (identity at lane 63); also returns the wave total.
 template <class V, class Op>
 __device__ __forceinline__ V wave_excl_suffix_scan(V v, Op op, V id, V *total) {
-    v = op(v, dmov<dpp::SHL1>(id, v));
-    v = op(v, dmov<dpp::SHL2>(id, v));
-    v = op(v, dmov<dpp::SHL4>(id, v));
-    v = op(v, dmov<dpp::SHL8>(id, v));
+    if constexpr (kBoxDpp<V, Op>) {
+        box_suffix_rows_dpp<std::is_same<Op, UniteOp>::value>(v);
+    } else {
+        v = op(v, dmov<dpp::SHL1>(id, v));
+        v = op(v, dmov<dpp::SHL2>(id, v));
+        v = op(v, dmov<dpp::SHL4>(id, v));
+        v = op(v, dmov<dpp::SHL8>(id, v));
+    }
     // lanes 16r hold row r's suffix; carry the later rows' product in
     const V t1 = rdlane(v, 16), t2 = rdlane(v, 32), t3 = rdlane(v, 48);
     const V r1 = op(t2, t3), r0 = op(t1, r1);
     const int row = (threadIdx.x & (WAVE - 1)) >> 4;
-    const V later = row == 0 ? r0 : row == 1 ? r1 : row == 2 ? t3 : id;
+    const V later = vsel(row == 0, r0, vsel(row == 1, r1, vsel(row == 2, t3, id)));
     v = op(v, later);
     *total = rdlane(v, 0);
     return dmov<dpp::WSHL1>(id, v);
 }
 
 // Exclusive scan over the NW*64 threads of a workgroup; `sh` holds NW values.
-// Also returns the workgroup total.  Contains two barriers.
-template <int NW, class V, class Op>
+// Also returns the workgroup total.  Contains two barriers (one when `sh` is
+// not used again, REUSE = false).
+template <int NW, class V, class Op, bool REUSE = true>
 __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *total) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     V inc = wave_incl_scan(v, op, ident);
@@ -355,7 +446,7 @@ __device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V *sh, V *tota
     }
     const V ex = dmov<dpp::WSHR1>(ident, inc);
     *total = tot;
-    __syncthreads();
+    if (REUSE) __syncthreads();  // `sh` may be written again after return
     return op(pre, ex);
 }
 
@@ -373,28 +464,6 @@ __device__ __forceinline__ uint32_t as_clip(uint32_t k) {
 
 // ----------------------------------------------------------- small helpers
 __device__ __forceinline__ int msb32(uint32_t x) { return 31 - __clz(x); }
-
-// position of the j-th (0-based) set bit of a KK-bit mask, or -1
-template <int KK = K>
-__device__ __forceinline__ int nth_bit(uint32_t mask, int j) {
-#pragma unroll
-    for (int p = 0; p < KK; ++p) {
-        if ((mask >> p) & 1u) {
-            if (j == 0) return p;
-            --j;
-        }
-    }
-    return -1;
-}
-
-template <class V, int N>
-__device__ __forceinline__ V pick(const V (&a)[N], int i) {
-    V r = a[0];
-#pragma unroll
-    for (int j = 1; j < N; ++j)
-        if (i == j) r = a[j];
-    return r;
-}
 
 // lower_bound over off[0..cnt): first index with off[idx] >= x
 __device__ __forceinline__ int64_t lower_bound64(const int64_t *off, int64_t cnt, int64_t x) {
@@ -507,17 +576,17 @@ __device__ __forceinline__ void mintree_build(int *mt, int v) {
     mt[WW + t] = v;
     // after step l, a lane whose low l bits are all set holds the min of its
     // aligned group of 2^l lanes (out-of-pattern lanes combine with themselves)
-    v = min(v, dmov<dpp::SHR1>(v, v));
+    v = min(v, dmov<dpp::SHR1>(INT32_MAX, v));
     if ((lane & 1) == 1) mt[(WW + t) >> 1] = v;
-    v = min(v, dmov<dpp::SHR2>(v, v));
+    v = min(v, dmov<dpp::SHR2>(INT32_MAX, v));
     if ((lane & 3) == 3) mt[(WW + t) >> 2] = v;
-    v = min(v, dmov<dpp::SHR4>(v, v));
+    v = min(v, dmov<dpp::SHR4>(INT32_MAX, v));
     if ((lane & 7) == 7) mt[(WW + t) >> 3] = v;
-    v = min(v, dmov<dpp::SHR8>(v, v));
+    v = min(v, dmov<dpp::SHR8>(INT32_MAX, v));
     if ((lane & 15) == 15) mt[(WW + t) >> 4] = v;
-    v = min(v, dmov<dpp::BC15, 0xA>(v, v));
+    v = min(v, dmov<dpp::BC15, 0xA>(INT32_MAX, v));
     if ((lane & 31) == 31) mt[(WW + t) >> 5] = v;
-    v = min(v, dmov<dpp::BC31, 0xC>(v, v));
+    v = min(v, dmov<dpp::BC31, 0xC>(INT32_MAX, v));
     if (lane == 63) mt[(WW + t) >> 6] = v;
     __syncthreads();
 }
@@ -535,48 +604,93 @@ __device__ __forceinline__ int mintree_node(const int *mt, int x) {
     return min(min(mt[4], mt[5]), min(mt[6], mt[7]));
 }
 
-// The wave levels of a union tree of boxes over the WW threads: leaves at
-// WW + t, internal nodes down to one node per wave (indices WW/64..WW/32-1),
-// and EMPTY at index 0.  No barrier; nodes above the wave level are not built.
-template <class V, int WW = W>
-__device__ __forceinline__ void uniontree_wave(V *ut, V v) {
+// The wave levels of a union tree over the WW threads (leaves at WW + t,
+// internal nodes down to one node per wave, i.e. indices WW/64..WW/32-1,
+// and EMPTY at index 0; nodes above the wave level are not built) and the
+// wave's exclusive prefix union, in one pass: after each inclusive-scan step
+// the lanes that close an aligned group of 2, 4, ... 64 lanes hold that
+// group's union, which is the tree node.  No barrier.
+template <class V, int WW>
+__device__ __forceinline__ V uniontree_scan(V *ut, V v, V *total) {
     const int t = threadIdx.x, lane = t & (WAVE - 1);
-    if (t == 0) ut[0] = Pay<V>::empty();  // the "no node" sentinel of uniontree_inner
+    if (t == 0) ut[0] = Pay<V>::empty();
     ut[WW + t] = v;
-    v = unite(v, dmov<dpp::SHR1>(v, v));
-    if ((lane & 1) == 1) ut[(WW + t) >> 1] = v;
-    v = unite(v, dmov<dpp::SHR2>(v, v));
-    if ((lane & 3) == 3) ut[(WW + t) >> 2] = v;
-    v = unite(v, dmov<dpp::SHR4>(v, v));
-    if ((lane & 7) == 7) ut[(WW + t) >> 3] = v;
-    v = unite(v, dmov<dpp::SHR8>(v, v));
-    if ((lane & 15) == 15) ut[(WW + t) >> 4] = v;
-    v = unite(v, dmov<dpp::BC15, 0xA>(v, v));
-    if ((lane & 31) == 31) ut[(WW + t) >> 5] = v;
-    v = unite(v, dmov<dpp::BC31, 0xC>(v, v));
-    if (lane == 63) ut[(WW + t) >> 6] = v;
-}
-
-// rightmost leaf s < t with leaf value < v, or -1
-template <int WW = W>
-__device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int64_t v) {
-    int x = WW + t;
-    while (x > 1) {
-        if ((x & 1) && (int64_t)mintree_node<WW>(mt, x - 1) < v) {
-            x = x - 1;
-            while (x < WW) x = ((int64_t)mintree_node<WW>(mt, 2 * x + 1) < v) ? 2 * x + 1 : 2 * x;
-            return x - WW;
-        }
-        x >>= 1;
+    if constexpr (std::is_same<V, Box>::value) {
+        box_unite_step<0>(v);
+        if ((lane & 1) == 1) ut[(WW + t) >> 1] = v;
+        box_unite_step<1>(v);
+        if ((lane & 3) == 3) ut[(WW + t) >> 2] = v;
+        box_unite_step<2>(v);
+        if ((lane & 7) == 7) ut[(WW + t) >> 3] = v;
+        box_unite_step<3>(v);
+        if ((lane & 15) == 15) ut[(WW + t) >> 4] = v;
+        box_unite_step<4>(v);
+        if ((lane & 31) == 31) ut[(WW + t) >> 5] = v;
+        box_unite_step<5>(v);
+        if (lane == 63) ut[(WW + t) >> 6] = v;
+        asm volatile("s_nop 1" ::: "memory");
+    } else {
+        v = unite(v, dmov<dpp::SHR1>(v, v));
+        if ((lane & 1) == 1) ut[(WW + t) >> 1] = v;
+        v = unite(v, dmov<dpp::SHR2>(v, v));
+        if ((lane & 3) == 3) ut[(WW + t) >> 2] = v;
+        v = unite(v, dmov<dpp::SHR4>(v, v));
+        if ((lane & 7) == 7) ut[(WW + t) >> 3] = v;
+        v = unite(v, dmov<dpp::SHR8>(v, v));
+        if ((lane & 15) == 15) ut[(WW + t) >> 4] = v;
+        v = unite(v, dmov<dpp::BC15, 0xA>(v, v));
+        if ((lane & 31) == 31) ut[(WW + t) >> 5] = v;
+        v = unite(v, dmov<dpp::BC31, 0xC>(v, v));
+        if (lane == 63) ut[(WW + t) >> 6] = v;
     }
-    return -1;
+    *total = rdlane(v, WAVE - 1);
+    return dmov<dpp::WSHR1>(Pay<V>::empty(), v);
 }
 
-// Union over leaves [lo, hi] of a tree built by uniontree_wave, for
+// Rightmost leaf s < t with leaf value < v, or -1.  The left siblings of
+// every ancestor of leaf t are read together (the lowest one below v holds
+// the answer), then the descent takes two levels per step, reading three
+// grandchildren at once.  Every read is unconditional (nodes above the wave
+// level come from the wave nodes), so the reads of a step are in flight
+// together rather than one dependent read per level.
+template <int WW = W>
+__device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int v) {
+    constexpr int NW = WW / WAVE;
+    static_assert(NW == 1 || NW == 2 || NW == 4, "one, two or four waves");
+    constexpr int LV = NW == 4 ? 8 : NW == 2 ? 7 : 6;  // levels below the root
+    // nodes 1 .. NW-1 (not stored)
+    int up1 = INT32_MAX, up2 = INT32_MAX, up3 = INT32_MAX;
+    if (NW == 4) {
+        const int4 wn = *reinterpret_cast<const int4 *>(mt + 4);
+        up2 = min(wn.x, wn.y), up3 = min(wn.z, wn.w), up1 = min(up2, up3);
+    }
+    const int x = WW + t;
+    int y = 0, lev = 0;
+    int cv[LV];
+#pragma unroll
+    for (int k = 0; k < LV; ++k) {
+        const int c = (x >> k) - 1;  // the left sibling when x >> k is a right child
+        const int m = mt[c >= NW ? c : NW];
+        cv[k] = !((x >> k) & 1) ? INT32_MAX : c >= NW ? m : c == 3 ? up3 : c == 2 ? up2 : up1;
+    }
+#pragma unroll
+    for (int k = LV - 1; k >= 0; --k)
+        if (cv[k] < v) y = (x >> k) - 1, lev = k;
+    if (y == 0) return -1;
+    while (lev >= 2) {
+        const int a3 = mt[4 * y + 3], a2 = mt[4 * y + 2], a1 = mt[4 * y + 1];
+        y = a3 < v ? 4 * y + 3 : a2 < v ? 4 * y + 2 : a1 < v ? 4 * y + 1 : 4 * y;
+        lev -= 2;
+    }
+    if (lev == 1) y = mt[2 * y + 1] < v ? 2 * y + 1 : 2 * y;
+    return y - WW;
+}
+
+// Union over leaves [lo, hi] of a tree built by uniontree_scan, for
 // 1 <= lo and hi <= WW-2 (EMPTY if lo > hi).  Such a range never covers a
 // node above the wave level (at most four waves), so seven levels suffice.
 // Straight-line: every LDS read is issued before the first is used; a level
-// that contributes nothing reads node 0, which uniontree_wave sets to EMPTY.
+// that contributes nothing reads node 0, which uniontree_scan sets to EMPTY.
 template <class V, int WW = W>
 __device__ __forceinline__ V uniontree_inner(const V *ut, int lo, int hi) {
     static_assert(WW / WAVE <= 4, "ranges inside at most four waves");

@@ -531,6 +531,9 @@ struct ResolveSmem {
     union Early {
         struct {
             V jval[BOXES ? WW : 1];
+            // the contexts after jumping (small payloads: their own array
+            // saves a barrier; larger ones overwrite jval, to keep LDS low)
+            V jfin[BOXES && sizeof(V) <= 24 ? WW : 1];
             int inc_idx[T + 1];
             // per thread: {lowest level (SENT after a scene start), owner
             // thread or -1, base level, first cx entry | unmatched-open mask
@@ -631,8 +634,8 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     const Walk wk = walk_kinds<KK>(ks, rm);
     const int b = __popc(wk.umask);
     SegU segtot;
-    const SegU ex = block_excl_scan<NW>(SegU{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a, b}, SegUOp{},
-                                           SegU{0, 0, 0}, sm.sh_seg, &segtot);
+    const SegU ex = block_excl_scan<NW, SegU, SegUOp, false>(SegU{wk.rs ? 1 : 0, wk.rs ? b : b - wk.a, b},
+                                                             SegUOp{}, SegU{0, 0, 0}, sm.sh_seg, &segtot);
     const int ub = aP + 1 + ex.u;  // this thread's first entry in cx
     const int Dt = ex.r ? ex.v : dP + ex.v;  // absolute depth at thread start
     const int pre_m = Dt - wk.a;
@@ -645,14 +648,17 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
             if (ks[j] == BCLIP) clipm |= 1u << j;
         sm.e.w.tinfo[t] = make_int4(cm, -1, base, (int)((uint32_t)ub | (wk.umask << 16) | ((clipm & wk.umask) << (16 + KK))));
     }
-    if (BOXES) {
+    {  // this thread's unmatched opens: element index (| BLEND_BIT) and clip prefix
         V c = Pay<V>::inf();
         int e = ub;
 #pragma unroll
         for (int p = 0; p < KK; ++p) {
             if ((wk.umask >> p) & 1u) {
-                if (ks[p] == BCLIP) c = isect(c, bx[p]);
-                if (e <= T) sm.cx[e] = c;
+                if (BOXES && ks[p] == BCLIP) c = isect(c, bx[p]);
+                if (e <= T) {
+                    sm.e.w.inc_idx[e] = (int)((g0 + p) | (ks[p] == BBLEND ? BLEND_BIT : 0u));
+                    if (BOXES) sm.cx[e] = c;
+                }
                 ++e;
             }
         }
@@ -736,8 +742,12 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
                 ptr = sm.e.w.jptr[ptr];
             }
         }
-        __syncthreads();  // every read of the published values is done
-        sm.e.w.jval[t] = v;
+        if (sizeof(V) <= 24) {
+            sm.e.w.jfin[t] = v;
+        } else {
+            __syncthreads();  // every read of the published values is done
+            sm.e.w.jval[t] = v;
+        }
         __syncthreads();
     } else {
         __syncthreads();  // publishes tlink
@@ -749,6 +759,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     // collected in registers and written once at the end.
     int64_t sid = off ? scene_of(off, S, g0) : 0;
     int soff = off ? (int)off[sid] : 0;
+    const int soff0 = soff;  // the thread's first scene
     uint32_t mask = 0;    // open positions on the local stack
     uint32_t clipm = 0;   // positions holding BEGIN_CLIP
     uint32_t leafm = 0;   // positions holding leaves (the only rows unions read)
@@ -757,7 +768,11 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     uint32_t lbm = 0;     // closes of blends opened in this thread
     uint32_t rchk = 0;    // typed brackets: closes whose open's token is checked after the walk
     uint32_t defmask = 0; // closes of blends opened before this thread
-    uint64_t errs = 0;    // status bits, 4 per element; element g0 - 1 at bit 4KK
+    uint32_t rmm = 0;     // closes whose open lies in an earlier thread of this partition
+    uint32_t recm = 0;    // closes that leave a close record
+    int crci[KK];         // close record index within this partition
+    using ErrT = std::conditional_t<(KK + 1) * 4 <= 32, uint32_t, uint64_t>;
+    ErrT errs = 0;        // status bits, 4 per element; element g0 - 1 at bit 4KK
     bool rseen = false;
     int dep = Dt;
     V octx[KK], res[KK];
@@ -787,7 +802,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         const bool real = i < un;
         const uint32_t bit = 1u << j;
         if ((rm >> j) & 1u) {
-            if (real && i > 0 && dep != 0) errs |= (uint64_t)ST_UNBAL << (j > 0 ? 4 * (j - 1) : 4 * KK);  // element i - 1
+            if (real && i > 0 && dep != 0) errs |= (ErrT)ST_UNBAL << (j > 0 ? 4 * (j - 1) : 4 * KK);  // element i - 1
             mask = 0;
             rseen = true;
             dep = 0;
@@ -796,58 +811,49 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
                 soff = (int)off[sid];
             }
         }
-        if (!BRK && real && kr[j] > 4u) errs |= (uint64_t)ST_BAD_KIND << (4 * j);
+        if (!BRK && real && kr[j] > 4u) errs |= (ErrT)ST_BAD_KIND << (4 * j);
         const int tp = mask ? msb32(mask) : -1;
         if (tp < 0 && !rseen && cur_L != dep) {
+            // straight-line lookup: the holder thread (levels above lowtop)
+            // or the incoming table; both name an entry of inc_idx and cx
             cur_L = dep;
-            cur_idx = -1;
-            cur_kind = -1;
-            cur_own = -1;
-            cur_ctx = Pay<V>::inf();
-            if (dep >= 1 && dep <= lowtop) {
-                const int x = dep - preM;
-                if (x >= 0 && x <= aP) {
-                    const int u = sm.e.w.inc_idx[x];
-                    const V c = BOXES ? sm.cx[x] : Pay<V>::inf();  // read together with u
-                    if (u != -1) {
-                        cur_idx = (int)((uint32_t)u & ~BLEND_BIT);
-                        cur_kind = ((uint32_t)u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
-                        cur_ctx = c;
-                    }
-                }
-            } else if (dep > lowtop) {
-                int4 ti = sm.e.w.tinfo[own_s >= 0 ? own_s : 0];
+            const bool tabp = dep <= lowtop;
+            int4 ti = make_int4(0, -1, 0, 0);
+            if (!tabp) {
+                ti = sm.e.w.tinfo[own_s >= 0 ? own_s : 0];
                 while (own_s >= 0 && ti.x >= dep) {
                     own_s = ti.y;
-                    if (own_s >= 0) ti = sm.e.w.tinfo[own_s];
-                }
-                const int s = own_s;
-                if (s >= 0) {
-                    const int jj = dep - ti.z - 1;
-                    const uint32_t um = ((uint32_t)ti.w >> 16) & ((1u << KK) - 1u);
-                    const int e = (ti.w & 0xFFFF) + (int)jj;
-                    if (jj >= 0 && jj < __popc(um) && e <= T) {
-                        const int p = nth_bit<KK>(um, (int)jj);
-                        cur_idx = (int)(p0 + (uint32_t)s * KK + p);
-                        if (BOXES) cur_ctx = isect(sm.e.w.jval[s], sm.cx[e]);
-                        cur_kind = (((uint32_t)ti.w >> (16 + KK + p)) & 1u) ? (int)BCLIP : (int)BBLEND;
-                        cur_own = s;
-                        cur_pos = p;
-                        cur_ent = e;
-                    }
+                    ti = sm.e.w.tinfo[own_s >= 0 ? own_s : 0];
                 }
             }
+            const int s = tabp ? -1 : own_s;
+            const int jj = dep - ti.z - 1;
+            const uint32_t um = ((uint32_t)ti.w >> 16) & ((1u << KK) - 1u);
+            const int eo = (ti.w & 0xFFFF) + jj;
+            const bool okown = s >= 0 && jj >= 0 && jj < (int)__popc(um) && eo <= T;
+            const int x = dep - preM;
+            const bool oktab = tabp && dep >= 1 && x >= 0 && x <= aP;
+            const int ent = oktab ? x : okown ? eo : 0;
+            const int u = sm.e.w.inc_idx[ent];
+            const V c = BOXES ? sm.cx[ent] : Pay<V>::inf();
+            const V jv = !BOXES ? Pay<V>::inf() : sizeof(V) <= 24 ? sm.e.w.jfin[okown ? s : 0] : sm.e.w.jval[okown ? s : 0];
+            const bool hit = (oktab || okown) && u != -1;
+            cur_idx = hit ? (int)((uint32_t)u & ~BLEND_BIT) : -1;
+            cur_kind = !hit ? -1 : ((uint32_t)u & BLEND_BIT) ? (int)BBLEND : (int)BCLIP;
+            if (BOXES) cur_ctx = vsel(hit, vsel(okown, isect(jv, c), c), Pay<V>::inf());
+            cur_own = hit && okown ? s : -1;
+            cur_pos = cur_idx - (int)(p0 + (uint32_t)s * KK);
+            cur_ent = eo;
         }
         // the top of the stack before this element: a local open, the scene
         // root after a reset, or the looked-up entry
-        int top = rseen ? -1 : cur_idx;
-        V ctx = rseen ? Pay<V>::inf() : cur_ctx;
+        int top = tp >= 0 ? (int)(g0 + tp) : rseen ? -1 : cur_idx;
+        V ctx = vsel(rseen, Pay<V>::inf(), cur_ctx);
+        if (BOXES && j > 0) {
+            uint32_t tpm = tp >= 0 ? 1u << tp : 0u;
+            asm("" : "+v"(tpm));  // opaque: selects, not an indexed load
 #pragma unroll
-        for (int q = 0; q < j; ++q) {
-            if (q == tp) {
-                top = (int)(g0 + q);
-                if (BOXES) ctx = octx[q];
-            }
+            for (int q = 0; q < j; ++q) ctx = vsel(((tpm >> q) & 1u) != 0, octx[q], ctx);
         }
         if (pm && real) pm[i] = top >= 0 ? (int32_t)(top - soff) : -1;
         // every case below is computed with selects: the wave runs one
@@ -870,10 +876,10 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         const uint32_t pbit = lclose ? (1u << tps) : 0u;
         if (BOXES) {
             const V ix = isect(ctx, bx[j]);
-            octx[j] = k == BCLIP ? ix : ctx;
+            octx[j] = vsel(k == BCLIP, ix, ctx);
             // leaf: its clipped box; BEGIN_CLIP: likewise; END_CLIP: the
             // context inside its open.  Blend rows are filled in later.
-            res[j] = canon((isleaf && Pay<V>::kLeafOwn) || k == BCLIP ? ix : ctx);
+            res[j] = canon(vsel((isleaf && Pay<V>::kLeafOwn) || k == BCLIP, ix, ctx));
         }
         bool mism;
         if (BRK) {
@@ -889,8 +895,8 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
             mism = (lclose && ((k == ECLIP) != (((clipm >> tps) & 1u) != 0))) ||
                    (rok && ((k == ECLIP) != (cur_kind == (int)BCLIP)));
         }
-        errs |= (real && mism) ? (uint64_t)ST_MISMATCH << (4 * j) : 0u;
-        errs |= (real && (rootclose || (rclose && !rok))) ? (uint64_t)ST_UNBAL << (4 * j) : 0u;
+        errs |= (real && mism) ? (ErrT)ST_MISMATCH << (4 * j) : 0u;
+        errs |= (real && (rootclose || (rclose && !rok))) ? (ErrT)ST_UNBAL << (4 * j) : 0u;
         leafm |= isleaf ? bit : 0u;
         clipm |= k == BCLIP ? bit : 0u;
         keep |= (isleaf || (k == BCLIP && !sclip) || (k == ECLIP && (lclose || (rok && !rec)))) ? bit : 0u;
@@ -903,17 +909,32 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
 #pragma unroll
         for (int q = 0; q < j; ++q)
             if (lclose && q == tp) mv[q] = (int32_t)(i - soff);
-        if (rok && !rec && match && real && (uint32_t)cur_idx < un) match[cur_idx] = (int32_t)(i - soff);
-        if (BOXES && rok && k == EBLEND && real) {
-            defmask |= bit;
-            dfw[j] = cur_own >= 0 ? (uint32_t)(cur_own + 1) | ((uint32_t)cur_pos << 9) | ((uint32_t)cur_ent << 12)
-                                  : (uint32_t)(dP - dep) << 12;
-        }
-        // the close's position, with the top bit set for a blend; the slot was
-        // written by the gather
-        if (rec) cr_c[rbase + ci] = (int32_t)(i | (k == EBLEND ? 0x80000000u : 0u));
+        // the open's match entry, written after the walk
+        rmm |= (rok && !rec && real && (uint32_t)cur_idx < un) ? bit : 0u;
+        const bool dfb = BOXES && rok && k == EBLEND && real;
+        defmask |= dfb ? bit : 0u;
+        dfw[j] = !dfb ? 0u
+                      : cur_own >= 0 ? (uint32_t)(cur_own + 1) | ((uint32_t)cur_pos << 9) | ((uint32_t)cur_ent << 12)
+                                     : (uint32_t)(dP - dep) << 12;
+        // close records, written after the walk
+        recm |= rec ? bit : 0u;
+        crci[j] = ci;
         mask = isopen ? (mask | bit) : (mask & ~pbit);
         dep += isopen ? 1 : (lclose || rclose) ? -1 : 0;
+    }
+    // pops of levels held by earlier threads or partitions happen before any
+    // scene start of this thread, so they share the thread's first scene
+    if (match && rmm) {
+#pragma unroll
+        for (int j = 0; j < KK; ++j)
+            if ((rmm >> j) & 1u) match[mv[j] + soff0] = (int32_t)(g0 + j - soff0);
+    }
+    if (BOXES && recm) {
+        // the close's position, with the top bit set for a blend; the slot
+        // was written by the gather
+#pragma unroll
+        for (int j = 0; j < KK; ++j)
+            if ((recm >> j) & 1u) cr_c[rbase + crci[j]] = (int32_t)((g0 + j) | (ks[j] == EBLEND ? 0x80000000u : 0u));
     }
     if (BRK && __ballot(rchk != 0)) {
         // closes of opens held by earlier threads: compare with the open's
@@ -926,7 +947,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
 #pragma unroll
         for (int j = 0; j < KK; ++j)
-            if (((rchk >> j) & 1u) && kr[j] != otok[j] + 1u) errs |= (uint64_t)ST_MISMATCH << (4 * j);
+            if (((rchk >> j) & 1u) && kr[j] != otok[j] + 1u) errs |= (ErrT)ST_MISMATCH << (4 * j);
     }
     if (errs) {  // malformed input only: raise each element's bits in its scene's word
 #pragma unroll
@@ -935,20 +956,38 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
             if (bj) flag(status, off, S, j < KK ? (int64_t)g0 + j : (int64_t)g0 - 1, bj);
         }
     }
-    // blends opened and closed in this thread: the union of the leaves between
+    // Leaf rows (EMPTY elsewhere) and their prefix unions pu[j] (leaves
+    // before position j), all with selects: every lane runs the same steps.
+    V pu[KK + 1], sa[KK];  // sa[p]: union of the leaves after position p
     if (BOXES) {
+        V lr[KK];
+#pragma unroll
+        for (int j = 0; j < KK; ++j) lr[j] = vsel(((leafm >> j) & 1u) != 0, res[j], Pay<V>::empty());
+        pu[0] = Pay<V>::empty();
+#pragma unroll
+        for (int j = 0; j < KK; ++j) pu[j + 1] = unite(pu[j], lr[j]);
+        sa[KK - 1] = Pay<V>::empty();
+#pragma unroll
+        for (int j = KK - 2; j >= 0; --j) sa[j] = unite(sa[j + 1], lr[j + 1]);
+        // blends opened and closed in this thread: the union of the leaves
+        // strictly between open p and close j
 #pragma unroll
         for (int j = 1; j < KK; ++j) {
-            if (!((lbm >> j) & 1u)) continue;
+            const bool lb = (lbm >> j) & 1u;
             const int p = (lbp >> (3 * j)) & 7u;
-            V u = Pay<V>::empty();
+            V acc = Pay<V>::empty(), u = Pay<V>::empty();
 #pragma unroll
-            for (int q = 1; q < j; ++q)
-                if (q > p && ((leafm >> q) & 1u)) u = unite(u, res[q]);
-            res[j] = u;
+            for (int q = j - 1; q >= 0; --q) {
+                u = vsel(q == p, acc, u);
+                acc = unite(acc, lr[q]);
+            }
+            res[j] = vsel(lb, u, res[j]);
+            // the open's row too; an opaque one-hot mask keeps the compiler
+            // from turning the selects into an indexed (scratch) store
+            uint32_t pm1 = lb ? 1u << p : 0u;
+            asm("" : "+v"(pm1));  // opaque to the compiler
 #pragma unroll
-            for (int q = 0; q < j; ++q)
-                if (q == p) res[q] = u;
+            for (int q = 0; q < j; ++q) res[q] = vsel(((pm1 >> q) & 1u) != 0, u, res[q]);
         }
 #pragma unroll
         for (int j = 0; j < KK; ++j)
@@ -965,29 +1004,19 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     // unions over threads come from wave scans plus the wave totals; only
     // blends opened and closed in different threads of this partition need
     // an arbitrary range, answered from a union tree over threads.
-    V ttot = Pay<V>::empty();
-#pragma unroll
-    for (int j = 0; j < KK; ++j)
-        if ((leafm >> j) & 1u) ttot = unite(ttot, res[j]);
+    const V ttot = pu[KK];
     const int wid = t >> 6;
-    V wtot_u;
-    const V wpre = wave_excl_scan(ttot, UniteOp{}, Pay<V>::empty(), &wtot_u);
     V wsuf_dummy;
     const V wsuf = wave_excl_suffix_scan(ttot, UniteOp{}, Pay<V>::empty(), &wsuf_dummy);
     __syncthreads();  // the walk's reads of the early tables and cx are done
-    uniontree_wave<V, WW>(ut, ttot);
+    V wtot_u;
+    const V wpre = uniontree_scan<V, WW>(ut, ttot, &wtot_u);
     if (lane == 0) sm.wtot[wid] = wtot_u;
-    {  // suffix unions after each of this thread's unmatched opens
-        V suf = Pay<V>::empty();
-        int e = ub + __popc(wk.umask);
+    // suffix unions after each of this thread's unmatched opens
 #pragma unroll
-        for (int p = KK - 1; p >= 0; --p) {
-            if ((wk.umask >> p) & 1u) {
-                --e;
-                if (e <= T) sm.cx[e] = suf;
-            }
-            if ((leafm >> p) & 1u) suf = unite(suf, res[p]);
-        }
+    for (int p = 0; p < KK; ++p) {
+        const int e = ub + (int)__popc(wk.umask & ((1u << p) - 1u));
+        if (((wk.umask >> p) & 1u) && e <= T) sm.cx[e] = sa[p];
     }
     __syncthreads();
     V pre_t = wpre, suf_t = wsuf, all = Pay<V>::empty();
@@ -1007,13 +1036,9 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
             dloc |= 1u << j;
             continue;
         }
-        V pre = Pay<V>::empty();
-#pragma unroll
-        for (int q = 0; q < j; ++q)
-            if ((leafm >> q) & 1u) pre = unite(pre, res[q]);
         const int ci = (int)(dfw[j] >> 12);
         if (ci < aP && (uint32_t)(rbase + ci) < un)
-            Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pre));
+            Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pu[j]));
     }
     // closes of blends opened in an earlier thread of this partition, taken
     // one per round so a wave runs as many rounds as its busiest lane needs
@@ -1021,12 +1046,14 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (!dloc) continue;
         const int j = __builtin_ctz(dloc);
         dloc &= dloc - 1;
-        uint32_t w = 0;
-        V pre = Pay<V>::empty();
+        uint32_t w = dfw[0];
+        V pre = pu[0];
+        uint32_t jm = 1u << j;
+        asm("" : "+v"(jm));  // opaque: the selects stay selects, not an indexed load
 #pragma unroll
-        for (int q = 0; q < KK; ++q) {
-            if (q == j) w = dfw[q];
-            if (q < j && ((leafm >> q) & 1u)) pre = unite(pre, res[q]);
+        for (int q = 1; q < KK; ++q) {
+            w = ((jm >> q) & 1u) ? dfw[q] : w;
+            pre = vsel(((jm >> q) & 1u) != 0, pu[q], pre);
         }
         const int s = (int)(w & 0x1FFu) - 1, pos = (int)((w >> 9) & 7u), ent = (int)(w >> 12);
         const V u = unite(unite(sm.cx[ent], uniontree_inner<V, WW>(ut, s + 1, t - 1)), pre);
