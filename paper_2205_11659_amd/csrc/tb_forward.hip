@@ -75,9 +75,10 @@ __global__ void k_offsets_flag(const uint32_t *flagw, int64_t S, uint32_t *statu
 
 // ---------------------------------------------------------------- k_reduce
 // One workgroup of W threads per partition, K consecutive elements per
-// thread (coalesced loads and stores).  Prefix and suffix bicyclic products
-// over threads come from DPP wave scans plus the four wave totals, so the
-// whole kernel needs two barriers.
+// thread (coalesced loads and stores).  The partition's bicyclic summary
+// comes from DPP wave scans plus the wave totals (one barrier; one more when
+// a scene starts in the partition), then the clip prefix of the surviving
+// opens (one more) and the staging of the surviving opens (one more).
 template <bool BOXES, class V, int KK, bool BRK = false>
 __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ kind,
                                               const float4 *__restrict__ box, int64_t n,
@@ -86,6 +87,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
                                               int32_t *__restrict__ U_idx, void *__restrict__ U_cum,
                                               const int64_t *__restrict__ n_dyn) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
+    __shared__ int4 sh_w[NW];  // per wave: scene start seen, depth sum, lowest depth
     __shared__ BicR sh_bic[NW];
     __shared__ V sh_b[NW];
     __shared__ int32_t sh_ui[T];
@@ -108,33 +110,71 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
         ks[j] = BRK ? bracket_kind(ks[j]) : ks[j] > 4u ? LEAF : Pay<V>::kAllOpens ? as_clip(ks[j]) : ks[j];
     const uint32_t rm = reset_mask<KK>(off, S, n, g0);
     const Walk wk = walk_kinds<KK>(ks, rm);
-    const BicR mine{wk.a, (int)__popc(wk.umask), wk.rs ? 1 : 0};
+    const int b = (int)__popc(wk.umask);
     V bxs[KK];
 
-    // prefix (earlier threads) and suffix (later threads) products
-    BicR wtot, wtot2;
-    BicR pre = wave_excl_scan(mine, BicROp{}, BicR{0, 0, 0}, &wtot);
-    BicR suf = wave_excl_suffix_scan(mine, BicROp{}, BicR{0, 0, 0}, &wtot2);
-    if (lane == 0) sh_bic[wid] = wtot;
+    // Without a scene start in the partition (the common case) the summary
+    // comes from plain integer scans: depth at each thread's start is the
+    // sum of the earlier threads' net changes (b - a), cm = that depth - a
+    // is the lowest depth the thread reaches, the partition pops -min cm of
+    // the incoming stack, and a thread's unmatched opens (levels base+1 ..
+    // base+b) survive unless a later thread reaches below them.  These are
+    // DPP-fused adds and mins.  With a scene start the bicyclic products of
+    // the threads (with resets) are scanned instead.
+    constexpr int NONE = 1 << 24;  // above every depth a partition reaches
+    const uint64_t rsb = __ballot(wk.rs);  // lanes of this wave with a scene start
+    int wt, wmin;
+    const int dl = wave_excl_scan(b - wk.a, AddOp{}, 0, &wt);
+    const int cml = dl - wk.a;
+    const int sufl = wave_excl_suffix_scan(cml, MinOp{}, NONE, &wmin);  // later lanes
+    if (lane == 0) sh_w[wid] = make_int4(rsb != 0ull, wt, wmin, 0);
     __syncthreads();
-    BicR before{0, 0, 0}, after{0, 0, 0}, tot{0, 0, 0};
+    bool anyr = false;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const BicR x = sh_bic[w];
-        if (w < wid) before = bicr(before, x);
-        tot = bicr(tot, x);
+    for (int w = 0; w < NW; ++w) anyr |= sh_w[w].x != 0;
+    int base, ns, tota, totb, totr;
+    if (!anyr) {  // block-uniform
+        int offw = 0, acc = 0, minA = NONE, laterMin = NONE;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int4 x = sh_w[w];
+            if (w == wid) offw = acc;
+            minA = min(minA, acc + x.z);
+            if (w > wid) laterMin = min(laterMin, acc + x.z);
+            acc += x.y;
+        }
+        tota = minA < 0 ? -minA : 0;
+        totb = acc + tota;
+        totr = 0;
+        base = offw + cml;
+        const int mAfter = min(sufl == NONE ? NONE : sufl + offw, laterMin);
+        ns = max(0, min(b, mAfter - base));
+    } else {
+        const BicR mine{wk.a, b, wk.rs ? 1 : 0};
+        BicR wtot, wtot2;
+        BicR pre = wave_excl_scan(mine, BicROp{}, BicR{0, 0, 0}, &wtot);
+        BicR suf = wave_excl_suffix_scan(mine, BicROp{}, BicR{0, 0, 0}, &wtot2);
+        if (lane == 0) sh_bic[wid] = wtot;
+        __syncthreads();
+        BicR before{0, 0, 0}, after{0, 0, 0}, tot{0, 0, 0};
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const BicR x = sh_bic[w];
+            if (w < wid) before = bicr(before, x);
+            tot = bicr(tot, x);
+        }
+#pragma unroll
+        for (int w = NW - 1; w >= 0; --w)
+            if (w > wid) after = bicr(sh_bic[w], after);
+        pre = bicr(before, pre);
+        suf = bicr(suf, after);
+        const int D = pre.r ? pre.b : pre.b - pre.a;  // partition-relative unless a reset came first
+        base = wk.rs ? 0 : D - wk.a;
+        // later threads pop the last `suf.a` of this thread's unmatched opens
+        ns = suf.r ? 0 : (b > suf.a ? b - suf.a : 0);
+        tota = tot.a, totb = tot.b, totr = tot.r;
     }
-#pragma unroll
-    for (int w = NW - 1; w >= 0; --w)
-        if (w > wid) after = bicr(sh_bic[w], after);
-    pre = bicr(before, pre);
-    suf = bicr(suf, after);
-    const int D = pre.r ? pre.b : pre.b - pre.a;  // partition-relative unless a reset came first
-    const int base = wk.rs ? 0 : D - wk.a;
-    const int baseP = tot.r ? 0 : -tot.a;
-    // later threads pop the last `suf.a` of this thread's unmatched opens
-    const int b = mine.b;
-    const int ns = suf.r ? 0 : (b > suf.a ? b - suf.a : 0);
+    const int baseP = totr ? 0 : -tota;
 
     // clip prefix over the partition's surviving opens
     uint32_t surv = 0;  // positions of this thread's surviving unmatched opens
@@ -169,7 +209,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
             if (w < wid) cum = isect(sh_b[w], cum);
     }
 
-    // surviving opens fill slots [0, tot.b): staged in LDS, then written
+    // surviving opens fill slots [0, totb): staged in LDS, then written
     // with consecutive lanes on consecutive slots
     const int64_t slot0 = (int64_t)base - baseP;  // first surviving open's slot
     int jj = 0;
@@ -186,12 +226,12 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
         }
     }
     __syncthreads();
-    const int nsv = tot.b < T ? tot.b : T;
+    const int nsv = totb < T ? totb : T;
     for (int sl = t; sl < nsv; sl += WW) {
         U_idx[P * T + sl] = sh_ui[sl];
         if (BOXES) Pay<V>::st(U_cum, P * T + sl, sh_uc[sl]);
     }
-    if (t == 0) pinfo[P] = make_int4(tot.a, tot.b, tot.r, 0);
+    if (t == 0) pinfo[P] = make_int4(tota, totb, totr, 0);
 }
 
 // ------------------------------------------------------------ spine kernels
