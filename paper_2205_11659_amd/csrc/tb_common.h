@@ -52,34 +52,56 @@ __device__ __forceinline__ void st_box(float4 *p, int64_t i, Box b) {
 }
 
 // Box with, per coordinate, the index of the input element attaining it
-// (the gradient's route).  max/min keep the attaining index; on equal values
-// the lower index wins, so the combine stays associative, commutative and
-// idempotent and every combine order yields the same (value, index) pair.
+// (the gradient's route), held as one 64-bit key per coordinate: the
+// value's order-preserving bits above 32 bits of index.  The minimum
+// coordinates (x0, y0) carry the index and the maximum coordinates (x1, y1)
+// its complement, so a union (a plain 64-bit min of x0, y0 and max of x1,
+// y1) takes the extreme value and, on equal values, the lower index; an
+// intersection flips the index bits around the same compare.  On equal
+// values the lower index always wins, so the combine stays associative,
+// commutative and idempotent and every combine order yields the same route.
+// -0 orders as +0, as the float comparison has them equal.
 struct BoxS {
-    float x0, y0, x1, y1;
-    int32_t s0, s1, s2, s3;
+    uint64_t k0, k1, k2, k3;
 };
 constexpr int32_t NOSRC = INT32_MAX;  // identity elements route nowhere
+constexpr uint64_t KLOW = 0xFFFFFFFFull;
 
-__device__ __forceinline__ void mx(float &v, int32_t &s, float w, int32_t t) {
-    if (w > v || (w == v && t < s)) v = w, s = t;
+__device__ __forceinline__ uint32_t ordf(float f) {
+    const uint32_t b = __float_as_uint(f == 0.0f ? 0.0f : f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
-__device__ __forceinline__ void mn(float &v, int32_t &s, float w, int32_t t) {
-    if (w < v || (w == v && t < s)) v = w, s = t;
+__device__ __forceinline__ uint64_t fkey(float f, uint32_t low) { return ((uint64_t)ordf(f) << 32) | low; }
+__device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a > b ? a : b; }
+// the larger value, the lower index on a tie (key holding the index)
+__device__ __forceinline__ uint64_t kmax_lo(uint64_t a, uint64_t b) { return (a ^ KLOW) > (b ^ KLOW) ? a : b; }
+// the smaller value, the lower index on a tie (key holding the complement)
+__device__ __forceinline__ uint64_t kmin_lo(uint64_t a, uint64_t b) { return (a ^ KLOW) < (b ^ KLOW) ? a : b; }
+__device__ __forceinline__ BoxS isect(const BoxS &a, const BoxS &b) {
+    return {kmax_lo(a.k0, b.k0), kmax_lo(a.k1, b.k1), kmin_lo(a.k2, b.k2), kmin_lo(a.k3, b.k3)};
 }
-__device__ __forceinline__ BoxS isect(BoxS a, const BoxS &b) {
-    mx(a.x0, a.s0, b.x0, b.s0), mx(a.y0, a.s1, b.y0, b.s1);
-    mn(a.x1, a.s2, b.x1, b.s2), mn(a.y1, a.s3, b.y1, b.s3);
-    return a;
+__device__ __forceinline__ BoxS unite(const BoxS &a, const BoxS &b) {
+    return {kmin(a.k0, b.k0), kmin(a.k1, b.k1), kmax(a.k2, b.k2), kmax(a.k3, b.k3)};
 }
-__device__ __forceinline__ BoxS unite(BoxS a, const BoxS &b) {
-    mn(a.x0, a.s0, b.x0, b.s0), mn(a.y0, a.s1, b.y0, b.s1);
-    mx(a.x1, a.s2, b.x1, b.s2), mx(a.y1, a.s3, b.y1, b.s3);
-    return a;
+__device__ __forceinline__ bool boxs_nonempty(const BoxS &a) {
+    return (uint32_t)(a.k0 >> 32) < (uint32_t)(a.k2 >> 32) && (uint32_t)(a.k1 >> 32) < (uint32_t)(a.k3 >> 32);
 }
-__device__ __forceinline__ BoxS canon(BoxS a) {
-    if (a.x0 < a.x1 && a.y0 < a.y1) return a;
-    return {INFINITY, INFINITY, -INFINITY, -INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
+__device__ __forceinline__ BoxS boxs_empty() {
+    return {fkey(INFINITY, NOSRC), fkey(INFINITY, NOSRC), fkey(-INFINITY, ~(uint32_t)NOSRC),
+            fkey(-INFINITY, ~(uint32_t)NOSRC)};
+}
+__device__ __forceinline__ BoxS canon(const BoxS &a) {
+    const bool ne = boxs_nonempty(a);
+    const BoxS e = boxs_empty();
+    return {ne ? a.k0 : e.k0, ne ? a.k1 : e.k1, ne ? a.k2 : e.k2, ne ? a.k3 : e.k3};
+}
+// the attaining element of coordinate c (NOSRC for none)
+__device__ __forceinline__ int32_t boxs_src(const BoxS &a, int c) {
+    return c == 0 ? (int32_t)(uint32_t)a.k0
+         : c == 1 ? (int32_t)(uint32_t)a.k1
+         : c == 2 ? (int32_t)~(uint32_t)a.k2
+                  : (int32_t)~(uint32_t)a.k3;
 }
 
 template <class V>
@@ -93,8 +115,7 @@ __device__ __forceinline__ Box vsel(bool c, const Box &a, const Box &b) {
     return {c ? a.x0 : b.x0, c ? a.y0 : b.y0, c ? a.x1 : b.x1, c ? a.y1 : b.y1};
 }
 __device__ __forceinline__ BoxS vsel(bool c, const BoxS &a, const BoxS &b) {
-    return {c ? a.x0 : b.x0, c ? a.y0 : b.y0, c ? a.x1 : b.x1, c ? a.y1 : b.y1,
-            c ? a.s0 : b.s0, c ? a.s1 : b.s1, c ? a.s2 : b.s2, c ? a.s3 : b.s3};
+    return {c ? a.k0 : b.k0, c ? a.k1 : b.k1, c ? a.k2 : b.k2, c ? a.k3 : b.k3};
 }
 
 // Payload traits: identities, own element, workspace load/store.
@@ -122,11 +143,10 @@ struct Pay<Box> {
 template <>
 struct Pay<BoxS> {
     static __device__ __forceinline__ BoxS inf() {
-        return {-INFINITY, -INFINITY, INFINITY, INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
+        return {fkey(-INFINITY, NOSRC), fkey(-INFINITY, NOSRC), fkey(INFINITY, ~(uint32_t)NOSRC),
+                fkey(INFINITY, ~(uint32_t)NOSRC)};
     }
-    static __device__ __forceinline__ BoxS empty() {
-        return {INFINITY, INFINITY, -INFINITY, -INFINITY, NOSRC, NOSRC, NOSRC, NOSRC};
-    }
+    static __device__ __forceinline__ BoxS empty() { return boxs_empty(); }
     static constexpr bool kUnions = true;
     static constexpr bool kLeafOwn = true;
     static constexpr bool kAllOpens = false;
@@ -134,19 +154,22 @@ struct Pay<BoxS> {
         return own(((const float4 *)base)[i], i);
     }
     static __device__ __forceinline__ BoxS own(float4 b, int64_t i) {
-        const int32_t s = (int32_t)i;
-        return {b.x, b.y, b.z, b.w, s, s, s, s};
+        const uint32_t s = (uint32_t)i;
+        return {fkey(b.x, s), fkey(b.y, s), fkey(b.z, ~s), fkey(b.w, ~s)};
     }
+    // rows of 32 bytes: two 16-byte halves
     static __device__ __forceinline__ BoxS ld(const void *base, int64_t i) {
-        const float4 v = ((const float4 *)base)[2 * i];
-        const int4 s = ((const int4 *)base)[2 * i + 1];
-        return {v.x, v.y, v.z, v.w, s.x, s.y, s.z, s.w};
+        const ulonglong2 a = ((const ulonglong2 *)base)[2 * i];
+        const ulonglong2 b = ((const ulonglong2 *)base)[2 * i + 1];
+        return {a.x, a.y, b.x, b.y};
     }
     static __device__ __forceinline__ void st(void *base, int64_t i, const BoxS &v) {
-        ((float4 *)base)[2 * i] = make_float4(v.x0, v.y0, v.x1, v.y1);
-        ((int4 *)base)[2 * i + 1] = make_int4(v.s0, v.s1, v.s2, v.s3);
+        ulonglong2 a, b;
+        a.x = v.k0, a.y = v.k1, b.x = v.k2, b.y = v.k3;
+        ((ulonglong2 *)base)[2 * i] = a;
+        ((ulonglong2 *)base)[2 * i + 1] = b;
     }
-    static __device__ __forceinline__ bool nonempty(const BoxS &v) { return v.x0 < v.x1 && v.y0 < v.y1; }
+    static __device__ __forceinline__ bool nonempty(const BoxS &v) { return boxs_nonempty(v); }
 };
 
 // A 2-D affine transform [a b c; d e f] on integer coordinates, arithmetic
@@ -213,9 +236,14 @@ __device__ __forceinline__ Box dmov(Box o, Box v) {
     return {dmov<C, RM>(o.x0, v.x0), dmov<C, RM>(o.y0, v.y0), dmov<C, RM>(o.x1, v.x1), dmov<C, RM>(o.y1, v.y1)};
 }
 template <int C, int RM = 0xF>
+__device__ __forceinline__ uint64_t dmov64(uint64_t o, uint64_t v) {
+    const uint32_t lo = (uint32_t)dmov<C, RM>((int)(uint32_t)o, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)dmov<C, RM>((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int C, int RM = 0xF>
 __device__ __forceinline__ BoxS dmov(BoxS o, BoxS v) {
-    return {dmov<C, RM>(o.x0, v.x0), dmov<C, RM>(o.y0, v.y0), dmov<C, RM>(o.x1, v.x1), dmov<C, RM>(o.y1, v.y1),
-            dmov<C, RM>(o.s0, v.s0), dmov<C, RM>(o.s1, v.s1), dmov<C, RM>(o.s2, v.s2), dmov<C, RM>(o.s3, v.s3)};
+    return {dmov64<C, RM>(o.k0, v.k0), dmov64<C, RM>(o.k1, v.k1), dmov64<C, RM>(o.k2, v.k2), dmov64<C, RM>(o.k3, v.k3)};
 }
 // uniform read of one lane
 __device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -225,9 +253,12 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 __device__ __forceinline__ Box rdlane(Box v, int l) {
     return {rdlane(v.x0, l), rdlane(v.y0, l), rdlane(v.x1, l), rdlane(v.y1, l)};
 }
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)rdlane((int)(uint32_t)v, l), hi = (uint32_t)rdlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ BoxS rdlane(BoxS v, int l) {
-    return {rdlane(v.x0, l), rdlane(v.y0, l), rdlane(v.x1, l), rdlane(v.y1, l),
-            rdlane(v.s0, l), rdlane(v.s1, l), rdlane(v.s2, l), rdlane(v.s3, l)};
+    return {rdlane64(v.k0, l), rdlane64(v.k1, l), rdlane64(v.k2, l), rdlane64(v.k3, l)};
 }
 
 template <int C, int RM = 0xF>
@@ -249,10 +280,13 @@ __device__ __forceinline__ Aff shfl_idx(Aff v, int src) {
 __device__ __forceinline__ Box shfl_idx(Box v, int src) {
     return {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE), __shfl(v.y1, src, WAVE)};
 }
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, WAVE);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ BoxS shfl_idx(BoxS v, int src) {
-    return {__shfl(v.x0, src, WAVE), __shfl(v.y0, src, WAVE), __shfl(v.x1, src, WAVE), __shfl(v.y1, src, WAVE),
-            __shfl((int)v.s0, src, WAVE), __shfl((int)v.s1, src, WAVE), __shfl((int)v.s2, src, WAVE),
-            __shfl((int)v.s3, src, WAVE)};
+    return {shfl64(v.k0, src), shfl64(v.k1, src), shfl64(v.k2, src), shfl64(v.k3, src)};
 }
 
 // Segmented sum: (r, v) with r = "a reset occurs in this range"; a reset

@@ -1311,10 +1311,10 @@ struct SinkGrad {
     __device__ __forceinline__ void emit(int64_t i, const BoxS &v) const {
         uint32_t m = 0;
         bool bad = false;
-        if (v.x0 < v.x1 && v.y0 < v.y1) {
+        if (boxs_nonempty(v)) {
             const float4 gv = g[i];
             const float gc[4] = {gv.x, gv.y, gv.z, gv.w};
-            const int32_t sc[4] = {v.s0, v.s1, v.s2, v.s3};
+            const int32_t sc[4] = {boxs_src(v, 0), boxs_src(v, 1), boxs_src(v, 2), boxs_src(v, 3)};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int64_t s = sc[c];
