@@ -7,7 +7,7 @@ import pytest
 
 import gen
 import oracle
-from gpu_util import same_bits, say, to_dev
+from gpu_util import gpu_bbox, same_bits, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -94,3 +94,24 @@ def test_autograd_function():
     ogi, _ = oracle.backward(kind, box, g)
     assert same_bits(out.detach().cpu().numpy(), oout)
     assert same_bits(bt.grad.cpu().numpy(), ogi)
+
+
+def test_signed_zero_ties():
+    """-0 and +0 compare equal: where they meet, the route goes to the lower
+    index as at any tie (the payload orders -0 as +0), and an output row's
+    zero may carry either sign, so rows are compared by value here."""
+    kind, box = nested_grid(20_000, 30, 5500, step=8.0)
+    box = box - np.float32(64.0)  # many coordinates exactly 0 on the grid
+    rng = np.random.default_rng(5501)
+    zero = box == 0
+    assert zero.sum() > 1000
+    box[zero & (rng.random(box.shape) < 0.5)] = np.float32(-0.0)
+    assert np.signbit(box[box == 0]).any() and (~np.signbit(box[box == 0])).any()
+    n = len(kind)
+    g = gen.normal(4 * n, 5502).reshape(n, 4)
+    check(kind, box, g, "signed zeros")
+    m, out, st = gpu_bbox(kind, box)
+    om, _, oout, ost = oracle.bbox(kind, box)
+    assert st == 0 and ost == 0
+    assert np.array_equal(m, om)
+    assert np.array_equal(out, oout)  # -0 == +0
