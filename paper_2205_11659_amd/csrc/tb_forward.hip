@@ -85,7 +85,7 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
                                               const int64_t *__restrict__ off, int64_t S,
                                               int4 *__restrict__ pinfo,
                                               int32_t *__restrict__ U_idx, void *__restrict__ U_cum,
-                                              const int64_t *__restrict__ n_dyn) {
+                                              const int64_t *__restrict__ n_dyn, uint32_t *__restrict__ zst) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
     __shared__ int4 sh_w[NW];  // per wave: scene start seen, depth sum, lowest depth
     __shared__ BicR sh_bic[NW];
@@ -95,6 +95,9 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
     const int64_t P = blockIdx.x;
     const int64_t g0 = P * T + (int64_t)t * KK;
+    // a single status word is cleared here rather than by a launch of its
+    // own (every later writer of it runs after this kernel)
+    if (zst && P == 0 && t == 0) *zst = 0u;
     if (n_dyn) {  // element count known on the device only: later partitions are empty
         n = *n_dyn;
         if (P * T >= n) {
@@ -1759,9 +1762,9 @@ constexpr bool kTunable = !BOXES || (std::is_same<V, Box>::value && std::is_same
 template <bool BOXES, class V, class SINK, int KD, bool BRK>
 static void launch_reduce(int64_t M, hipStream_t st, const uint32_t *kind, const float4 *box, int64_t n,
                           const int64_t *off, int64_t S, int4 *pinfo, int32_t *U_idx, void *U_cum,
-                          const int64_t *n_dyn) {
+                          const int64_t *n_dyn, uint32_t *zst) {
     k_reduce<BOXES, V, KD, BRK><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum,
-                                                               n_dyn);
+                                                               n_dyn, zst);
 }
 
 // BRK: the kinds are typed bracket tokens (matching alone)
@@ -1770,7 +1773,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
                                const int64_t *off, int64_t S, int32_t *match, int32_t *pm,
                                SINK sink, char *w, const FwdLayout &L, uint32_t *status,
                                hipStream_t st, const int64_t *n_dyn = nullptr,
-                               Variant var = Variant{}) {
+                               Variant var = Variant{}, uint32_t *zst = nullptr) {
     if (!kTunable<BOXES, V, SINK> || !variant_ok(var)) var = default_variant(BOXES);
     const int64_t M = L.M;
     int4 *pinfo = (int4 *)(w + L.pinfo);
@@ -1782,9 +1785,9 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     void *U_cum = w + L.U_cum;
     // elements per thread of the reduce
     if (var.kd == 8)
-        launch_reduce<BOXES, V, SINK, 8, BRK>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+        launch_reduce<BOXES, V, SINK, 8, BRK>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn, zst);
     else
-        launch_reduce<BOXES, V, SINK, 4, BRK>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn);
+        launch_reduce<BOXES, V, SINK, 4, BRK>(M, st, kind, box, n, off, S, pinfo, U_idx, U_cum, n_dyn, zst);
     {
         int4 *bagg = (int4 *)(w + L.bagg);
         const int64_t nbk = (M + SB - 1) / SB;
@@ -1873,10 +1876,13 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     return hipGetLastError();
 }
 
+// Clears the status words (and the offsets flag).  With `defer` (one scene,
+// n > 0) nothing is launched: the pipeline's first kernel clears the word.
 static uint32_t *prep_status(char *w, const FwdLayout &L, const int64_t *off, int64_t S,
-                             int64_t n, uint32_t *status, hipStream_t st) {
+                             int64_t n, uint32_t *status, hipStream_t st, bool defer = false) {
     const int64_t nstat = off ? S : 1;
     if (!status) status = (uint32_t *)(w + L.status);
+    if (defer && !off && n > 0) return status;
     uint32_t *flagw = (uint32_t *)(w + L.offflag);
     k_zero_status<<<(unsigned)((nstat + 255) / 256), 256, 0, st>>>(status, nstat, flagw);
     if (off) {
@@ -1891,13 +1897,14 @@ hipError_t fwd_run(bool boxes, const uint32_t *kind, const float4 *box, int64_t 
                    void *ws, uint32_t *status, hipStream_t st, Variant var) {
     const FwdLayout L = fwd_layout(n, off ? S : 1, sizeof(Box), false);
     char *w = (char *)ws;
-    status = prep_status(w, L, off, S, n, status, st);
+    status = prep_status(w, L, off, S, n, status, st, true);
     if (n == 0) return hipGetLastError();
+    uint32_t *zst = off ? nullptr : status;
     if (boxes)
         return run_pipeline<true, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w,
-                                                L, status, st, nullptr, var);
+                                                L, status, st, nullptr, var, zst);
     return run_pipeline<false, Box, SinkOut>(kind, box, n, off, S, match, pm, SinkOut{out}, w, L,
-                                             status, st, nullptr, var);
+                                             status, st, nullptr, var, zst);
 }
 
 // ------------------------------------------------- no-allocation variant
@@ -1945,10 +1952,10 @@ hipError_t brackets_run(const uint32_t *tok, int64_t n, int32_t *match, int32_t 
                         uint32_t *status, hipStream_t st, Variant var) {
     const FwdLayout L = fwd_layout(n, 1, sizeof(Box), false);
     char *w = (char *)ws;
-    status = prep_status(w, L, nullptr, 1, n, status, st);
+    status = prep_status(w, L, nullptr, 1, n, status, st, true);
     if (n == 0) return hipGetLastError();
     return run_pipeline<false, Box, SinkOut, true>(tok, nullptr, n, nullptr, 1, match, pm, SinkOut{nullptr},
-                                                   w, L, status, st, nullptr, var);
+                                                   w, L, status, st, nullptr, var, status);
 }
 
 ComposeF32Layout compose_f32_layout(int64_t n) {
@@ -2044,10 +2051,10 @@ hipError_t compose_run(const uint32_t *kind, const void *xf, int64_t n, void *ou
                        uint32_t *status, hipStream_t st) {
     const FwdLayout L = fwd_layout(n, 1, sizeof(Aff), false);
     char *w = (char *)ws;
-    status = prep_status(w, L, nullptr, 1, n, status, st);
+    status = prep_status(w, L, nullptr, 1, n, status, st, true);
     if (n == 0) return hipGetLastError();
     return run_pipeline<true, Aff, SinkAff>(kind, (const float4 *)xf, n, nullptr, 1, nullptr, nullptr,
-                                            SinkAff{out}, w, L, status, st);
+                                            SinkAff{out}, w, L, status, st, nullptr, Variant{}, status);
 }
 
 StreamLayout stream_layout(int64_t n) {
@@ -2101,14 +2108,14 @@ hipError_t bwd_run(const uint32_t *kind, const float4 *box, const float4 *grad_o
                    float4 *grad_in, void *ws, uint32_t *status, hipStream_t st) {
     const FwdLayout L = fwd_layout(n, 1, sizeof(BoxS), true);
     char *w = (char *)ws;
-    status = prep_status(w, L, nullptr, 1, n, status, st);
+    status = prep_status(w, L, nullptr, 1, n, status, st, true);
     if (n == 0) return hipGetLastError();
     unsigned long long *acc = (unsigned long long *)(w + L.acc);
     uint8_t *selfm = (uint8_t *)(w + L.selfm);
     k_zero_u64<<<(unsigned)((4 * n + 255) / 256), 256, 0, st>>>(acc, 4 * n);
     hipError_t e = run_pipeline<true, BoxS, SinkGrad>(kind, box, n, nullptr, 1, nullptr, nullptr,
                                                       SinkGrad{grad_out, acc, selfm, n, status}, w, L,
-                                                      status, st);
+                                                      status, st, nullptr, Variant{}, status);
     if (e != hipSuccess) return e;
     k_grad_final<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(grad_out, acc, selfm, grad_in, n);
     return hipGetLastError();
