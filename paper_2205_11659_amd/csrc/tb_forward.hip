@@ -565,6 +565,25 @@ __device__ int64_t incoming_slot(int64_t L, const int4 *runs, int nruns, int4 he
 template <bool BOXES, class V, int KK>
 struct ResolveSmem {
     static constexpr int WW = T / KK, NW = WW / WAVE;
+    struct EarlyTables {
+        V jval[BOXES ? WW : 1];
+        // the contexts after jumping (small payloads: their own array
+        // saves a barrier; larger ones overwrite jval, to keep LDS low)
+        V jfin[BOXES && sizeof(V) <= 24 ? WW : 1];
+        int inc_idx[T + 1];
+        // per thread: {lowest level (SENT after a scene start), owner
+        // thread or -1, base level, first cx entry | unmatched-open mask
+        // << 16 | mask of those that are clips << (16 + KK)}; one LDS
+        // read per owner-chain hop
+        int4 tinfo[WW];
+        int mt[2 * WW];
+        int jptr[WW];
+    };
+    // per wave, the in-partition cross-thread blend closes gathered into the
+    // space the early tables leave beside the union tree
+    static constexpr int UTB = (BOXES ? 2 * WW : 1) * (int)sizeof(V);
+    static constexpr int DCAP_RAW = ((int)sizeof(EarlyTables) - UTB) / (NW * (8 + (int)sizeof(V)));
+    static constexpr int DCAP = DCAP_RAW > 0 ? DCAP_RAW : 1;
     int4 runs[RMAX];
     // Until the walk ends: the clip context at each thread's base level, the
     // incoming levels [preM, dP] (entry x = level preM + x: the open's
@@ -572,21 +591,13 @@ struct ResolveSmem {
     // the min tree and the jumping pointers.  Afterwards: the union tree
     // over threads, which overlays them all.
     union Early {
-        struct {
-            V jval[BOXES ? WW : 1];
-            // the contexts after jumping (small payloads: their own array
-            // saves a barrier; larger ones overwrite jval, to keep LDS low)
-            V jfin[BOXES && sizeof(V) <= 24 ? WW : 1];
-            int inc_idx[T + 1];
-            // per thread: {lowest level (SENT after a scene start), owner
-            // thread or -1, base level, first cx entry | unmatched-open mask
-            // << 16 | mask of those that are clips << (16 + KK)}; one LDS
-            // read per owner-chain hop
-            int4 tinfo[WW];
-            int mt[2 * WW];
-            int jptr[WW];
-        } w;
+        EarlyTables w;
         V ut[BOXES ? 2 * WW : 1];
+        struct {
+            V ut_space[BOXES ? 2 * WW : 1];
+            int2 item[NW * DCAP];
+            V pre[NW * DCAP];
+        } d;
     } e;
     static_assert(KK <= 8 && T < 0xFFFF, "tinfo packs two KK-bit masks above a 16-bit entry");
     // Clip contexts.  Entries [0, aP] belong to the incoming levels; from
@@ -1083,8 +1094,43 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (ci < aP && (uint32_t)(rbase + ci) < un)
             Pay<V>::st(cr_pre, rbase + ci, unite(pre_t, pu[j]));
     }
-    // closes of blends opened in an earlier thread of this partition, taken
-    // one per round so a wave runs as many rounds as its busiest lane needs
+    // Closes of blends opened in an earlier thread of this partition.  A
+    // wave gathers its lanes' closes into LDS and then takes them 64 at a
+    // time, one per lane, so the union-tree queries do not run as many
+    // rounds as the busiest lane has closes; closes past the buffer stay
+    // with their lane and are taken one per round.
+    {
+        constexpr int DCAP = ResolveSmem<BOXES, V, KK>::DCAP;
+        const int nd = (int)__popc(dloc);
+        int wnd;
+        const int doff = wave_excl_scan(nd, AddOp{}, 0, &wnd);
+        const int wb = wid * DCAP;
+        int k = doff;
+#pragma unroll
+        for (int j = 0; j < KK; ++j) {
+            if (!((dloc >> j) & 1u)) continue;
+            if (k < DCAP) {
+                sm.e.d.item[wb + k] = make_int2((int)(dfw[j] | ((uint32_t)j << 24)), t);
+                sm.e.d.pre[wb + k] = pu[j];
+                dloc &= ~(1u << j);
+            }
+            ++k;
+        }
+        asm volatile("" ::: "memory");  // a wave's LDS accesses complete in order
+        const int nbuf = min(wnd, DCAP);
+        for (int i0 = 0; i0 < nbuf; i0 += WAVE) {
+            const int i = i0 + lane;
+            if (i >= nbuf) continue;
+            const int2 it2 = sm.e.d.item[wb + i];
+            const V pre = sm.e.d.pre[wb + i];
+            const uint32_t w = (uint32_t)it2.x & 0xFFFFFFu;
+            const int j = (int)((uint32_t)it2.x >> 24), tt = it2.y;
+            const int s = (int)(w & 0x1FFu) - 1, pos = (int)((w >> 9) & 7u), ent = (int)(w >> 12);
+            const V u = unite(unite(sm.cx[ent], uniontree_inner<V, WW>(ut, s + 1, tt - 1)), pre);
+            sink.emit(p0 + (uint32_t)tt * KK + j, u);
+            sink.emit(p0 + (uint32_t)s * KK + pos, u);
+        }
+    }
     for (int it = 0; it < KK && __ballot(dloc != 0); ++it) {
         if (!dloc) continue;
         const int j = __builtin_ctz(dloc);
