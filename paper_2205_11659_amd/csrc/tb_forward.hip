@@ -92,7 +92,8 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     __shared__ V sh_b[NW];
     __shared__ int32_t sh_ui[T];
     __shared__ V sh_uc[BOXES ? T : 1];
-    const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t >> 6;
+    const int t = threadIdx.x, lane = t & (WAVE - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: scalar loops over waves
     const int64_t P = blockIdx.x;
     const int64_t g0 = P * T + (int64_t)t * KK;
     // a single status word is cleared here rather than by a launch of its
@@ -626,6 +627,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     __shared__ ResolveSmem<BOXES, V, KK> sm;
     V *ut = sm.e.ut;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: scalar loops over waves
     // Element indices and levels fit in 32 bits (n < 2^31); element indices
     // are unsigned so that a last partition past 2^31 - T cannot overflow.
     const uint32_t P = blockIdx.x;
@@ -738,7 +740,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     // partition: they come from earlier partitions (the LDS table).
 #pragma unroll
     for (int w = 0; w < NW - 1; ++w)
-        if (w < (t >> 6)) premin = min(premin, sm.e.w.mt[NW + w]);  // wave nodes of the min tree
+        if (w < wid) premin = min(premin, sm.e.w.mt[NW + w]);  // wave nodes of the min tree
     const int lowtop = min(premin, Dt);
     // lowest level any later thread reaches: an unmatched open of this thread
     // at a level not above it survives the partition
@@ -746,7 +748,7 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     int sufmin = wave_excl_suffix_scan(cm, MinOp{}, INT32_MAX, &wmin1);
 #pragma unroll
     for (int w = 1; w < NW; ++w)
-        if (w > (t >> 6)) sufmin = min(sufmin, sm.e.w.mt[NW + w]);
+        if (w > wid) sufmin = min(sufmin, sm.e.w.mt[NW + w]);
     // owner links between threads: the entry just below a thread's lowest
     // level belongs to the nearest earlier thread with a smaller lowest level
     const int tl = wk.rs ? -1 : mintree_prev_less<WW>(sm.e.w.mt, t, cm);
@@ -1059,7 +1061,6 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     // blends opened and closed in different threads of this partition need
     // an arbitrary range, answered from a union tree over threads.
     const V ttot = pu[KK];
-    const int wid = t >> 6;
     V wsuf_dummy;
     const V wsuf = wave_excl_suffix_scan(ttot, UniteOp{}, Pay<V>::empty(), &wsuf_dummy);
     __syncthreads();  // the walk's reads of the early tables and cx are done
