@@ -79,14 +79,16 @@ __global__ void k_offsets_flag(const uint32_t *flagw, int64_t S, uint32_t *statu
 // comes from DPP wave scans plus the wave totals (one barrier; one more when
 // a scene starts in the partition), then the clip prefix of the surviving
 // opens (one more) and the staging of the surviving opens (one more).
-template <bool BOXES, class V, int KK, bool BRK = false>
+template <bool BOXES, class V, int KK, bool BRK = false, bool BAT = true>
 __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ kind,
                                               const float4 *__restrict__ box, int64_t n,
-                                              const int64_t *__restrict__ off, int64_t S,
+                                              const int64_t *__restrict__ off_in, int64_t S,
                                               int4 *__restrict__ pinfo,
                                               int32_t *__restrict__ U_idx, void *__restrict__ U_cum,
                                               const int64_t *__restrict__ n_dyn, uint32_t *__restrict__ zst) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
+    // scene offsets (null for a single scene: a compile-time constant then)
+    const int64_t *const off = BAT ? off_in : nullptr;
     __shared__ int4 sh_w[NW];  // per wave: scene start seen, depth sum, lowest depth
     __shared__ BicR sh_bic[NW];
     __shared__ V sh_b[NW];
@@ -612,10 +614,10 @@ struct ResolveSmem {
     V wtot[NW];  // union of each wave's leaves
 };
 
-template <bool BOXES, class V, class SINK, int KK, bool BRK = false>
+template <bool BOXES, class V, class SINK, int KK, bool BRK = false, bool BAT = true>
 __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) void k_resolve(
     const uint32_t *__restrict__ kind, const float4 *__restrict__ box, int64_t n,
-    const int64_t *__restrict__ off, int64_t S, const int4 *__restrict__ pinfo,
+    const int64_t *__restrict__ off_in, int64_t S, const int4 *__restrict__ pinfo,
     const int4 *__restrict__ part, const int4 *__restrict__ runs_g,
     const int4 *__restrict__ rhead_g, const void *__restrict__ base_ctx,
     const int32_t *__restrict__ U_idx, const void *__restrict__ U_cum,
@@ -624,6 +626,8 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
     int32_t *__restrict__ match, int32_t *__restrict__ pm, SINK sink,
     uint32_t *__restrict__ status, const int64_t *__restrict__ n_dyn) {
     constexpr int WW = T / KK, NW = WW / WAVE;  // threads and waves per partition
+    // scene offsets (null for a single scene: a compile-time constant then)
+    const int64_t *const off = BAT ? off_in : nullptr;
     __shared__ ResolveSmem<BOXES, V, KK> sm;
     V *ut = sm.e.ut;  // valid once the walk is over
     const int t = threadIdx.x, lane = t & (WAVE - 1), wbase = t & ~(WAVE - 1);
@@ -1810,8 +1814,12 @@ template <bool BOXES, class V, class SINK, int KD, bool BRK>
 static void launch_reduce(int64_t M, hipStream_t st, const uint32_t *kind, const float4 *box, int64_t n,
                           const int64_t *off, int64_t S, int4 *pinfo, int32_t *U_idx, void *U_cum,
                           const int64_t *n_dyn, uint32_t *zst) {
-    k_reduce<BOXES, V, KD, BRK><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx, U_cum,
-                                                               n_dyn, zst);
+    if (off)
+        k_reduce<BOXES, V, KD, BRK, true><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx,
+                                                                         U_cum, n_dyn, zst);
+    else
+        k_reduce<BOXES, V, KD, BRK, false><<<(unsigned)M, T / KD, 0, st>>>(kind, box, n, off, S, pinfo, U_idx,
+                                                                          U_cum, n_dyn, zst);
 }
 
 // BRK: the kinds are typed bracket tokens (matching alone)
@@ -1880,9 +1888,14 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     // the partition-level steps among fewer threads)
     auto resolve = [&](auto kr) {
         constexpr int KR = decltype(kr)::value;
-        k_resolve<BOXES, V, SINK, KR, BRK><<<(unsigned)M, T / KR, 0, st>>>(
-            kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx, U_cum, U_suf, crbase,
-            cr_slot, cr_c, cr_pre, ptot, match, pm, sink, status, n_dyn);
+        if (off)
+            k_resolve<BOXES, V, SINK, KR, BRK, true><<<(unsigned)M, T / KR, 0, st>>>(
+                kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx, U_cum, U_suf, crbase,
+                cr_slot, cr_c, cr_pre, ptot, match, pm, sink, status, n_dyn);
+        else
+            k_resolve<BOXES, V, SINK, KR, BRK, false><<<(unsigned)M, T / KR, 0, st>>>(
+                kind, box, n, off, S, pinfo, part, runs, rhead, jv[cur], U_idx, U_cum, U_suf, crbase,
+                cr_slot, cr_c, cr_pre, ptot, match, pm, sink, status, n_dyn);
     };
     if constexpr (kTunable<BOXES, V, SINK>) {
         if (var.kr == 8)
