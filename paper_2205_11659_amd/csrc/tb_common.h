@@ -728,16 +728,16 @@ __device__ __forceinline__ int mintree_prev_less(const int *mt, int t, int v) {
 template <class V, int WW = W>
 __device__ __forceinline__ V uniontree_inner(const V *ut, int lo, int hi) {
     static_assert(WW / WAVE <= 4, "ranges inside at most four waves");
+    // Level k of the half-open range [l, h) is [ceil(l / 2^k), floor(h / 2^k)):
+    // its odd left end and its odd right end are the nodes taken there.
     V r = Pay<V>::empty();
-    int l = lo + WW, h = hi + WW + 1;
+    const uint32_t l = (uint32_t)(lo + WW), h = (uint32_t)(hi + WW + 1);
 #pragma unroll
     for (int lev = 0; lev < 7; ++lev) {
-        const bool go = l < h;
-        const bool ul = go && (l & 1), uh = go && (h & 1);
-        r = unite(r, ut[ul ? l : 0]);
-        r = unite(r, ut[uh ? h - 1 : 0]);
-        l = (l + (ul ? 1 : 0)) >> 1;
-        h = (h - (uh ? 1 : 0)) >> 1;
+        const uint32_t lk = (l + ((1u << lev) - 1u)) >> lev, hk = h >> lev;
+        const bool go = lk < hk;
+        r = unite(r, ut[go && (lk & 1u) ? lk : 0u]);
+        r = unite(r, ut[go && (hk & 1u) ? hk - 1u : 0u]);
     }
     return r;
 }
