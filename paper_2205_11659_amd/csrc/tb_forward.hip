@@ -419,25 +419,23 @@ __global__ void k_spine_link(const int4 *__restrict__ pinfo, int4 *__restrict__ 
     Pay<V>::st(jval, P, val);
 }
 
+// owners a pointer-jumping round covers per input pointer (JH^r after r rounds)
+constexpr int JH = 8;
+
 template <class V>
 __global__ void k_jump(const int32_t *__restrict__ ptr_in, const void *__restrict__ val_in,
                        int32_t *__restrict__ ptr_out, void *__restrict__ val_out, int64_t M) {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= M) return;
-    // Two hops per round (3^r partitions after r rounds, so fewer launches):
-    // the value two owners up, then one owner up, then this partition's, in
-    // ancestor-first order.
+    // JH - 1 hops per round, so fewer launches: each hop puts the next
+    // owner's value in front (ancestor-first order).
     int32_t p = ptr_in[P];
     V v = Pay<V>::ld(val_in, P);
-    if (p >= 0) {
-        const int32_t pp = ptr_in[p];
-        const V vp = Pay<V>::ld(val_in, p);
-        if (pp >= 0) {
-            v = isect(Pay<V>::ld(val_in, pp), isect(vp, v));
-            p = ptr_in[pp];
-        } else {
-            v = isect(vp, v);
-            p = -1;
+#pragma unroll
+    for (int h = 1; h < JH; ++h) {
+        if (p >= 0) {
+            v = isect(Pay<V>::ld(val_in, p), v);
+            p = ptr_in[p];
         }
     }
     ptr_out[P] = p;
@@ -1870,7 +1868,7 @@ static hipError_t run_pipeline(const uint32_t *kind, const float4 *box, int64_t 
     } else {
         k_spine_link<BOXES, V><<<gM, 256, 0, st>>>(pinfo, part, M, mtree, L.Mp, U_cum, jp[0], jv[0]);
         if (BOXES) {
-            for (int64_t reach = 1; reach < M; reach *= 3) {  // reach: owners covered so far
+            for (int64_t reach = 1; reach < M; reach *= JH) {  // reach: owners covered so far
                 k_jump<V><<<gM, 256, 0, st>>>(jp[cur], jv[cur], jp[cur ^ 1], jv[cur ^ 1], M);
                 cur ^= 1;
             }
