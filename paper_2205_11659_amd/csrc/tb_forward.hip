@@ -197,22 +197,31 @@ __global__ __launch_bounds__(T / KK) void k_reduce(const uint32_t *__restrict__ 
     V cum = Pay<V>::inf();
     if (BOXES) {
         // boxes of the clip opens that survive the partition
+        uint32_t sc = 0;
 #pragma unroll
         for (int p = 0; p < KK; ++p)
-            bxs[p] = (((surv >> p) & 1u) && ks[p] == BCLIP) ? Pay<V>::in(box, g0 + p) : Pay<V>::inf();
-        V agg = Pay<V>::inf();
+            if (((surv >> p) & 1u) && ks[p] == BCLIP) sc |= 1u << p;
 #pragma unroll
-        for (int p = 0; p < KK; ++p)
-            if ((surv >> p) & 1u) agg = isect(agg, bxs[p]);
-        V wagg;
-        cum = wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &wagg);
+        for (int p = 0; p < KK; ++p) bxs[p] = ((sc >> p) & 1u) ? Pay<V>::in(box, g0 + p) : Pay<V>::inf();
+        // a wave without surviving clip opens has the identity for every
+        // product (most waves of a partition that is not in a deep chain)
+        V wagg = Pay<V>::inf();
+        if (__ballot(sc != 0)) {
+            V agg = Pay<V>::inf();
+#pragma unroll
+            for (int p = 0; p < KK; ++p)
+                if ((sc >> p) & 1u) agg = isect(agg, bxs[p]);
+            cum = wave_excl_scan(agg, IsectOp{}, Pay<V>::inf(), &wagg);
+        }
         if (lane == 0) sh_b[wid] = wagg;
         __syncthreads();
         // earlier waves' products go in front, nearest wave first (the
-        // combine need not be commutative)
+        // combine need not be commutative); only waves with opens to stage
+        if (__ballot(surv != 0)) {
 #pragma unroll
-        for (int w = NW - 2; w >= 0; --w)
-            if (w < wid) cum = isect(sh_b[w], cum);
+            for (int w = NW - 2; w >= 0; --w)
+                if (w < wid) cum = isect(sh_b[w], cum);
+        }
     }
 
     // surviving opens fill slots [0, totb): staged in LDS, then written
