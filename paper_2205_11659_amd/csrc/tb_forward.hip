@@ -887,11 +887,16 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
             const bool tabp = dep <= lowtop;
             int4 ti = make_int4(0, -1, 0, 0);
             if (!tabp) {
-                ti = sm.e.w.tinfo[own_s >= 0 ? own_s : 0];
-                while (own_s >= 0 && ti.x >= dep) {
-                    own_s = ti.y;
-                    ti = sm.e.w.tinfo[own_s >= 0 ? own_s : 0];
+                // each hop reads a record's lowest level and owner link in
+                // one 8-byte LDS read; the rest of the record after the walk
+                const int2 *txy = reinterpret_cast<const int2 *>(sm.e.w.tinfo);
+                int2 xy = txy[2 * (own_s >= 0 ? own_s : 0)];
+                while (own_s >= 0 && xy.x >= dep) {
+                    own_s = xy.y;
+                    xy = txy[2 * (own_s >= 0 ? own_s : 0)];
                 }
+                const int2 zw = txy[2 * (own_s >= 0 ? own_s : 0) + 1];
+                ti = make_int4(xy.x, xy.y, zw.x, zw.y);
             }
             const int s = tabp ? -1 : own_s;
             const int jj = dep - ti.z - 1;
