@@ -304,7 +304,9 @@ tb_status tb_bbox_stream(const uint32_t *tag, const tb_box *box_in, int64_t n, i
  * depend on the variant.  Calls of tb_match, tb_bbox and tb_bbox_batched
  * use, for their size class ceil(log2 n), the variant chosen for the
  * current device kind (architecture and compute-unit count), else the
- * default (4, 4, 4 for boxes; 8, 8, 4 for matching alone).
+ * default (4, 4, 4 for boxes; 8, 8, 4 for matching alone).  Matching with
+ * parents (pm non-NULL) runs 4 elements per thread in the main pass whatever
+ * the variant (8 is slower there).
  *
  * tb_tune_*: same arguments as the call they tune, plus `reps`; each
  * candidate variant runs one warm-up and `reps` timed calls on the caller's
