@@ -105,6 +105,27 @@ def test_batched_empty_scenes():
     check_batched(kind, box, off2, "with empty scenes")
 
 
+@pytest.mark.parametrize("n", [1000, 5000, 300_001])
+def test_single_scene_instances_agree(n):
+    """tb_bbox runs kernel instances compiled without scene offsets; a batched
+    call with one scene runs the instances that search them.  Both must give
+    the same bits, and the same status for a malformed scene (whose other
+    outputs are unspecified)."""
+    kind, box = gen.walk(n, 64, 9900 + n, gen.BOX_NESTED_ALL)
+    bad = kind.copy()
+    bad[n // 3] = 2  # an extra END_CLIP
+    for tag, k in (("well formed", kind), ("malformed", bad)):
+        say(f"[single vs batched] {tag} n={n}")
+        m1, o1, s1 = gpu_bbox(k, box)
+        m2, o2, s2 = gpu_batched(k, box, np.array([0, n], np.int64))
+        assert s1 == int(s2[0]), (tag, s1, s2)
+        if tag == "well formed":
+            assert s1 == 0
+            assert np.array_equal(m1, m2) and same_bits(o1, o2), tag
+        else:
+            assert s1 != 0
+
+
 def test_batched_workload_2048():
     c = gen.config(3)
     check_batched(c["kind"], c["box"], c["offsets"], "2048 ragged")
