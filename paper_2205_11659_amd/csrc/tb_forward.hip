@@ -669,6 +669,11 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
 #pragma unroll
         for (int j = 0; j < KK; ++j) bx[j] = (g0 + j < n) ? Pay<V>::in(box, g0 + j) : Pay<V>::empty();
     }
+    uint32_t spos[SINK::kPos ? KK : 1];  // output positions of this thread's rows
+    if constexpr (SINK::kPos) {
+#pragma unroll
+        for (int j = 0; j < KK; ++j) spos[j] = (g0 + j < n) ? sink.pos(g0 + j) : ~0u;
+    }
     if (t < RMAX) sm.runs[t] = runs_g[P * RMAX + t];
 #pragma unroll
     for (int j = 0; j < KK; ++j)
@@ -1063,7 +1068,12 @@ __global__ __launch_bounds__(T / KK) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
 #pragma unroll
         for (int j = 0; j < KK; ++j)
-            if (((keep >> j) & 1u) && g0 + j < un) sink.emit(g0 + j, res[j]);
+            if (((keep >> j) & 1u) && g0 + j < un) {
+                if constexpr (SINK::kPos)
+                    sink.emit_at(spos[j], res[j]);
+                else
+                    sink.emit(g0 + j, res[j]);
+            }
     }
     if (match) {
 #pragma unroll
@@ -1337,6 +1347,7 @@ __global__ __launch_bounds__(W) void k_cross(const int *__restrict__ crtot, int6
 // ------------------------------------------------------------------ sinks
 // Forward: node boxes are written out.
 struct SinkOut {
+    static constexpr bool kPos = false;  // rows go to element indices
     float4 *out;
     __device__ __forceinline__ void emit(int64_t i, const Box &v) const { st_box(out, i, v); }
 };
@@ -1345,17 +1356,22 @@ struct SinkOut {
 // stream positions (idx[i] < ns; any other value is dropped, which only
 // stale workspace entries of malformed input can hold).
 struct SinkScatter {
+    // k_resolve reads a thread's own positions with its inputs (pos) and
+    // writes those rows with emit_at, so no store waits on a position load
+    static constexpr bool kPos = true;
     float4 *out;
     const int32_t *idx;
     uint32_t ns;
-    __device__ __forceinline__ void emit(int64_t i, const Box &v) const {
-        const uint32_t j = (uint32_t)idx[i];
+    __device__ __forceinline__ uint32_t pos(int64_t i) const { return (uint32_t)idx[i]; }
+    __device__ __forceinline__ void emit_at(uint32_t j, const Box &v) const {
         if (j < ns) st_box(out, j, v);
     }
+    __device__ __forceinline__ void emit(int64_t i, const Box &v) const { emit_at(pos(i), v); }
 };
 
 // Composition down the tree: each row's transform is written out.
 struct SinkAff {
+    static constexpr bool kPos = false;
     void *out;
     __device__ __forceinline__ void emit(int64_t i, const Aff &v) const { Pay<Aff>::st(out, i, v); }
 };
@@ -1369,6 +1385,7 @@ constexpr uint32_t ST_GRAD_RANGE = 16u;
 __device__ __forceinline__ bool grad_in_range(float g) { return fabsf(g) < 2147483648.0f; }
 
 struct SinkGrad {
+    static constexpr bool kPos = false;
     const float4 *g;
     unsigned long long *acc;  // [n][4] two's-complement sums on the 2^-32 grid
     uint8_t *selfm;           // [n] bit c: row i routes coordinate c to itself
